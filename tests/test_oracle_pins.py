@@ -1,0 +1,525 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: closed forms
+the integrals reduce to, identities of the ISRS profile, values the paper
+prints, independent library quadrature (scipy / QUADPACK), brute-force
+transcriptions of the literal equations on tiny grids, and limits.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.integrate as si
+
+import oracle
+from paper_2412_11614_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+TWO_PI = 2.0 * math.pi
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, name)) as fh:
+        return json.load(fh)
+
+
+def _beta(alpha_db, beta2, beta3, a, b, c):
+    """Propagation-constant mismatch from the Taylor series of beta(f) in
+    2 pi f -- an independent route to the phase coefficient of Eq. 24."""
+    def bet(f):
+        w = TWO_PI * f
+        return beta2 * w ** 2 / 2.0 + beta3 * w ** 3 / 6.0
+    return bet(a) + bet(b) - bet(c) - bet(a + b - c)
+
+
+# --------------------------------------------------------------------------
+# Building blocks
+# --------------------------------------------------------------------------
+
+def test_gauss_legendre_rule_exact_on_polynomials():
+    x, w = oracle.gl_rule()
+    assert abs(w.sum() - 2.0) < 1e-14
+    for k in range(0, 127):
+        exact = 0.0 if k % 2 else 2.0 / (k + 1)
+        assert abs(np.sum(w * x ** k) - exact) < 1e-13
+
+
+@pytest.mark.parametrize("wv", [20.5j, 21.0j - 0.3, 25.0j + 0.5, 30.0j - 2.0, 24.0 + 0.0j])
+def test_chebyshev_moments_two_routes_agree(wv):
+    """Forward recurrence and Gauss-Legendre evaluation of the modified moments
+    agree where both are valid."""
+    a = oracle.moments(wv, 16, "gl")
+    b = oracle.moments(wv, 16, "rec")
+    assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(a))
+
+
+def test_moments_closed_forms():
+    # M_0 = 2 sinh(w)/w, M_1 = 2 cosh(w)/w - 2 sinh(w)/w^2
+    for wv in [0.3 + 0.0j, 3.0j, 40.0j - 1.0, 7.0 + 2.0j]:
+        m = oracle.moments(wv, 4)
+        assert abs(m[0] - 2 * np.sinh(wv) / wv) < 1e-13 * abs(m[0]) + 1e-15
+        m1 = 2 * np.cosh(wv) / wv - 2 * np.sinh(wv) / wv ** 2
+        assert abs(m[1] - m1) < 1e-12 * max(abs(m1), 1e-3)
+
+
+def test_alpha_conversion_20db_over_100km():
+    """0.2 dB/km over 100 km is 20 dB: rho(L) with Cr = 0 is exactly 1/100."""
+    al = oracle.alpha_lin(0.2)
+    assert abs(oracle.rho(al, 0.0, 0.1, 10.0, 100.0, 0.3) - 0.01) < 1e-15
+
+
+def test_phase_coefficient_matches_taylor_mismatch():
+    """chi of Eq. 24 equals -(beta(a)+beta(b)-beta(c)-beta(a+b-c)) from the
+    Taylor expansion of the propagation constant."""
+    rng = np.random.default_rng(0)
+    for _ in range(200):
+        a, b, c = rng.uniform(-7.5, 7.5, 3)
+        b2, b3 = rng.uniform(-25, -18), rng.uniform(0.0, 0.2)
+        chi = oracle.phase_coef(b2, b3, a, b, c)
+        ref = -_beta(0.2, b2, b3, a, b, c)
+        assert abs(chi - ref) <= 1e-9 * max(1.0, abs(ref))
+    # peak efficiency on the axes f1 = f or f2 = f (Fig. 3 discussion)
+    assert oracle.phase_coef(-21.7, 0.14, 0.4, 2.0, 0.4) == 0.0
+    assert oracle.phase_coef(-21.7, 0.14, 2.0, -0.4, -0.4) == 0.0
+
+
+def test_spectrum_normalisation_and_shape():
+    for rs, ro in [(0.064, 0.1), (0.096, 0.04), (0.1, 0.0), (0.032, 0.5)]:
+        W_ = (1 + ro) * rs
+        val, _ = si.quad(lambda x: oracle.S(x, rs, ro) ** 2, -W_ / 2, W_ / 2, limit=200,
+                         points=[-(1 - ro) * rs / 2, (1 - ro) * rs / 2])
+        assert abs(rs * val - 1.0) < 1e-9          # Rs * int |S|^2 = 1
+        assert abs(oracle.S(0.0, rs, ro) - 1.0 / rs) < 1e-12
+        assert oracle.S(0.51 * W_ * 1.0001 + 1e-9, rs, ro) == 0.0
+        if ro > 0:
+            assert oracle.S(W_ / 2, rs, ro) < 1e-6 / rs
+
+
+# --------------------------------------------------------------------------
+# ISRS profile (Appendix A)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("X", [1e-6, 0.1, 0.5, 2.4, 6.0])
+def test_srs_gain_conserves_total_power(X):
+    """(1/B) int_{-B/2}^{B/2} SRS_G df = 1: ISRS only moves power (Eq. 14)."""
+    B = 10.0
+    val, _ = si.quad(lambda f: oracle.srs_gain(X, f, B), -B / 2, B / 2, epsabs=0, epsrel=1e-13)
+    assert abs(val / B - 1.0) < 1e-12
+
+
+def test_srs_gain_limits():
+    assert oracle.srs_gain(0.0, 3.0, 10.0) == 1.0
+    # zeta -> 0 continuity (no cancellation at tiny X)
+    assert abs(oracle.srs_gain(1e-12, 3.0, 10.0) - 1.0) < 1e-11
+    # low-frequency side gains, high-frequency side loses
+    assert oracle.srs_gain(1.0, -4.0, 10.0) > 1.0 > oracle.srs_gain(1.0, 4.0, 10.0)
+    assert oracle.leff(0.046, 0.0) == 0.0
+
+
+def test_delta_rho_matches_printed_values():
+    g = _golden("paper_delta_rho.json")
+    for c in g["cases"]:
+        al = oracle.alpha_lin(c["alpha_db_km"])
+        p = 1e-3 * 10 ** (c["ptot_dbm"] / 10)
+        v = oracle.delta_rho_db(p, c["cr"], al, c["length_km"], c["btot_thz"])
+        assert abs(v - c["printed_db"]) < g["tolerance_db"], (c["name"], v)
+
+
+# --------------------------------------------------------------------------
+# FWM efficiency factor mu (Eqs. 4-10, 23)
+# --------------------------------------------------------------------------
+
+def _rand_points(rng, n, half_band):
+    pts = []
+    for _ in range(n):
+        a, b, c = rng.uniform(-half_band, half_band, 3)
+        pts.append((a, b, c))
+    return pts
+
+
+@pytest.mark.parametrize("method", ["integral", "segment", "maclaurin"])
+def test_mu_cr0_is_gn_closed_form(method):
+    """With Cr = 0 every form reduces to (exp((i chi - alpha) L) - 1)/(i chi - alpha),
+    the classic GN efficiency (Eq. 6)."""
+    rng = np.random.default_rng(1)
+    for L, adb in [(80.0, 0.2), (100.0, 0.17), (57.3, 0.22)]:
+        sp = W.make_spans([L], alpha=adb, beta2=-21.7, beta3=0.14, cr=0.0)
+        al = adb / (10 / math.log(10))
+        for a, b, c in _rand_points(rng, 40, 5.0):
+            # chi itself is pinned by test_phase_coefficient_matches_taylor_mismatch;
+            # here it only feeds the closed form
+            chi = oracle.phase_coef(-21.7, 0.14, a, b, c)
+            bt = complex(-al, chi)
+            exact = (np.exp(bt * L) - 1) / bt
+            v = oracle.mu(sp, 0.1, 10.0, a, b, c, method)
+            # phase rounding: ~1e-16 relative in chi L moves the far-end term
+            cond = 1e-14 * abs(chi) * L * abs(np.exp(bt * L) / bt)
+            assert abs(v - exact) <= 1e-11 * abs(exact) + cond, (a, b, c, method)
+
+
+def test_mu_peak_efficiency_is_one_on_axes():
+    """|mu / L_eff| = 1 where (f1 - f)(f2 - f) = 0 at Cr = 0 (Fig. 3)."""
+    sp = W.make_spans([100.0], alpha=0.2, cr=0.0)
+    Leff = (1 - 0.01) / (0.2 / (10 / math.log(10)))
+    for a, b, c in [(0.3, -2.0, 0.3), (-4.0, 1.0, 1.0), (0.0, 0.0, 0.0)]:
+        for m in ["integral", "segment", "maclaurin"]:
+            assert abs(abs(oracle.mu(sp, 0.1, 1.0, a, b, c, m)) / Leff - 1.0) < 1e-13
+
+
+def test_mu_integral_matches_quadpack_qawo():
+    """The adaptive Chebyshev-moment quadrature agrees with QUADPACK's QAWO
+    (scipy quad with cos/sin weights) on strongly oscillating integrands."""
+    rng = np.random.default_rng(2)
+    L, adb, cr, ptot, B = 100.0, 0.2, 1.12, 10 ** 1.9 * 1e-3, 1.0201
+    sp = W.make_spans([L], alpha=adb, beta2=-21.68, beta3=0.0, cr=cr)
+    al = adb / (10 / math.log(10))
+    for a, b, c in _rand_points(rng, 12, 0.5):
+        x = a + b - c
+        chi = oracle.phase_coef(-21.68, 0.0, a, b, c)
+
+        def rho(z):
+            X = B * ptot * cr * (1 - math.exp(-al * z)) / al
+            g = 1.0 if X == 0 else X * math.exp(-X * x / B) / (2 * math.sinh(X / 2))
+            return g * math.exp(-al * z)
+
+        re, _ = si.quad(rho, 0, L, weight="cos", wvar=chi, epsabs=0, epsrel=1e-12, limit=500)
+        im, _ = si.quad(rho, 0, L, weight="sin", wvar=chi, epsabs=0, epsrel=1e-12, limit=500)
+        v = oracle.mu(sp, ptot, B, a, b, c, "integral")
+        assert abs(v - complex(re, im)) <= 1e-9 * abs(complex(re, im)), (a, b, c, chi)
+
+
+def test_mu_integral_matches_plain_adaptive_quadrature():
+    """Where chi L is moderate, plain adaptive Gauss-Kronrod on the raw
+    integrand agrees too."""
+    L, adb, cr, ptot, B = 80.0, 0.2, 0.028, 0.1, 10.0
+    sp = W.make_spans([L], alpha=adb, beta2=-21.7, beta3=0.14, cr=cr)
+    al = adb / (10 / math.log(10))
+    for a, b, c in [(0.05, 0.02, 0.0), (-0.2, 0.1, 0.05), (1.0, 0.01, 0.0), (3.0, 2.96, 2.95)]:
+        x = a + b - c
+        chi = oracle.phase_coef(-21.7, 0.14, a, b, c)
+        assert abs(chi * L) < 2e3
+
+        def f(z, part):
+            X = B * ptot * cr * (1 - math.exp(-al * z)) / al
+            g = X * math.exp(-X * x / B) / (2 * math.sinh(X / 2)) if X else 1.0
+            v = g * math.exp(-al * z) * complex(math.cos(chi * z), math.sin(chi * z))
+            return v.real if part == 0 else v.imag
+
+        re, _ = si.quad(f, 0, L, args=(0,), epsabs=0, epsrel=1e-12, limit=2000)
+        im, _ = si.quad(f, 0, L, args=(1,), epsabs=0, epsrel=1e-12, limit=2000)
+        v = oracle.mu(sp, ptot, B, a, b, c, "integral")
+        assert abs(v - complex(re, im)) <= 1e-10 * abs(complex(re, im))
+
+
+def test_segment_form_is_exact_integral_of_piecewise_constant_gain():
+    """Eqs. 8-9: the segment sum equals the integral of the integrand with
+    SRS_G frozen at each segment midpoint (Eq. 10)."""
+    L, adb, cr, ptot, B, dz = 87.3, 0.19, 1.12, 0.0794, 1.02, 1.0
+    sp = W.make_spans([L], alpha=adb, beta2=-21.7, beta3=0.0, cr=cr)
+    al = adb / (10 / math.log(10))
+    K = math.ceil(L / dz)
+    for a, b, c in [(0.1, 0.05, 0.0), (0.3, -0.2, 0.1), (0.45, 0.4, 0.0)]:
+        x = a + b - c
+        chi = oracle.phase_coef(-21.7, 0.0, a, b, c)
+        tot = 0j
+        for k in range(K):
+            z0, z1 = k * L / K, (k + 1) * L / K
+            zk = (k + 0.5) * L / K
+            X = B * ptot * cr * (1 - math.exp(-al * zk)) / al
+            g = X * math.exp(-X * x / B) / (2 * math.sinh(X / 2))
+            re, _ = si.quad(lambda z: math.exp(-al * z) * math.cos(chi * z), z0, z1, epsabs=0, epsrel=1e-13)
+            im, _ = si.quad(lambda z: math.exp(-al * z) * math.sin(chi * z), z0, z1, epsabs=0, epsrel=1e-13)
+            tot += g * complex(re, im)
+        v = oracle.mu(sp, ptot, B, a, b, c, "segment", dz=dz)
+        assert abs(v - tot) <= 1e-11 * abs(tot)
+
+
+def test_segment_converges_second_order_in_dz():
+    """The midpoint-frozen gain is a second-order rule: halving dz divides the
+    error against the integral form by about 4."""
+    L, adb, cr, ptot, B = 100.0, 0.2, 1.12, 0.0794, 1.02
+    sp = W.make_spans([L], alpha=adb, beta2=-21.7, beta3=0.0, cr=cr)
+    # points on and near the axes, where the phase is slow enough for the
+    # asymptotic regime at these dz
+    for a, b, c in [(0.3, 0.0, 0.0), (0.0, -0.4, 0.0), (0.45, 0.1, 0.1), (0.005, 0.01, 0.0)]:
+        ref = oracle.mu(sp, ptot, B, a, b, c, "integral")
+        errs = [abs(oracle.mu(sp, ptot, B, a, b, c, "segment", dz=d) - ref) for d in (2.0, 1.0, 0.5, 0.25)]
+        ratios = [errs[i] / errs[i + 1] for i in range(3)]
+        for r in ratios:
+            assert 3.9 < r < 4.1, ratios
+
+
+def test_maclaurin_is_exact_integral_of_linearised_profile():
+    """Eq. 4 is the exact integral of (1 - zeta f) exp(-alpha z) exp(i chi z), Eq. 3."""
+    L, adb, cr, ptot, B = 100.0, 0.2, 0.28, 0.0794, 1.02
+    sp = W.make_spans([L], alpha=adb, beta2=-21.7, beta3=0.0, cr=cr)
+    al = adb / (10 / math.log(10))
+    for a, b, c in [(0.1, 0.05, 0.0), (0.3, -0.2, 0.1), (0.45, -0.4, 0.0)]:
+        x = a + b - c
+        chi = oracle.phase_coef(-21.7, 0.0, a, b, c)
+
+        def f(z, part):
+            zeta = ptot * cr * (1 - math.exp(-al * z)) / al
+            v = (1 - zeta * x) * math.exp(-al * z)
+            return v * (math.cos(chi * z) if part == 0 else math.sin(chi * z))
+
+        re, _ = si.quad(f, 0, L, args=(0,), epsabs=0, epsrel=1e-13, limit=2000)
+        im, _ = si.quad(f, 0, L, args=(1,), epsabs=0, epsrel=1e-13, limit=2000)
+        v = oracle.mu(sp, ptot, B, a, b, c, "maclaurin")
+        assert abs(v - complex(re, im)) <= 1e-10 * abs(complex(re, im))
+
+
+# --------------------------------------------------------------------------
+# Link function (Eq. 22)
+# --------------------------------------------------------------------------
+
+def test_upsilon_phased_array_identical_spans():
+    """N identical spans, Cr = 0, gains restoring the launch profile:
+    |Upsilon|^2 = gamma^2 |eta_1|^2 sin^2(N chi L/2) / sin^2(chi L/2)."""
+    L, adb, gam = 80.0, 0.2, 1.3
+    al = adb / (10 / math.log(10))
+    for n_sp in (2, 7, 40):
+        spans = W.make_spans(np.full(n_sp, L), alpha=adb, beta2=-21.7, beta3=0.14, gamma=gam, cr=0.0)
+        for a, b, c in [(0.013, 0.021, 0.0), (0.5, -0.3, 0.0), (4.9, -4.8, 0.1), (7.0, 7.0, -0.2)]:
+            chi = oracle.phase_coef(-21.7, 0.14, a, b, c)
+            th = chi * L
+            if abs(math.sin(th / 2)) < 1e-3:
+                continue
+            bt = complex(-al, chi)
+            eta1 = (np.exp(bt * L) - 1) / bt
+            ref = gam ** 2 * abs(eta1) ** 2 * math.sin(n_sp * th / 2) ** 2 / math.sin(th / 2) ** 2
+            v = oracle.upsilon(spans, 0.1, 10.0, a, b, c, "integral")
+            assert abs(abs(v) ** 2 - ref) <= 1e-7 * max(ref, gam ** 2 * abs(eta1) ** 2 * 1e-3), (n_sp, a, b, th)
+
+
+def test_upsilon_symmetric_in_f1_f2():
+    spans = W.make_spans([80.0, 95.0, 61.0], alpha=[0.2, 0.18, 0.21], beta2=-21.7, beta3=0.14, cr=0.03)
+    for a, b, c in [(0.3, -1.2, 0.1), (4.0, 2.0, -3.0)]:
+        for m in ["integral", "segment", "maclaurin"]:
+            for g in (oracle.GAIN_EQUALIZED, oracle.GAIN_LOSS_ONLY):
+                u1 = oracle.upsilon(spans, 0.1, 10.0, a, b, c, m, gain_mode=g)
+                u2 = oracle.upsilon(spans, 0.1, 10.0, b, a, c, m, gain_mode=g)
+                assert u1 == u2
+
+
+def test_loss_only_gain_at_cr0_equals_equalized():
+    """With Cr = 0 a loss-only amplifier restores the flat launch profile, so
+    both gain readings coincide."""
+    spans = W.make_spans([80.0, 95.0], alpha=[0.2, 0.18], cr=0.0)
+    for a, b, c in [(0.3, -1.2, 0.1), (4.0, 2.0, -3.0)]:
+        u1 = oracle.upsilon(spans, 0.1, 10.0, a, b, c, "segment", gain_mode=oracle.GAIN_EQUALIZED)
+        u2 = oracle.upsilon(spans, 0.1, 10.0, a, b, c, "segment", gain_mode=oracle.GAIN_LOSS_ONLY)
+        assert abs(u1 - u2) <= 1e-12 * abs(u1)
+
+
+# --------------------------------------------------------------------------
+# Integration domain, islands and EGN terms (Eqs. 15-21)
+# --------------------------------------------------------------------------
+
+def test_domain_geometry_matches_paper():
+    g = _golden("paper_domain_geometry.json")
+    wl = W.table1_1thz()
+    B = wl.spectrum.n_ch * wl.spectrum.spacing_thz
+    for c in g["cases"]:
+        v = oracle.domain_max_d1d2(wl.spectrum, 10, c["index"]) / B ** 2
+        assert abs(v - c["fraction_of_btot2"]) <= g["relative_tolerance"] * c["fraction_of_btot2"], (c, v)
+
+
+@pytest.mark.parametrize("ratio,expect_side", [(0.6, False), (2.0 / 3.0 - 1e-6, False), (0.7, True), (1.0, True)])
+def test_side_islands_exist_iff_bandwidth_above_two_thirds_spacing(ratio, expect_side):
+    """With f = 0 the l = +-1 islands are empty iff B_ch <= 2/3 spacing (Sec. II-B)."""
+    sp = W.spectrum_from(5, 0.1, 0.1 * ratio, 0.0, np.full(5, 1e-3), ["gaussian"] * 5)
+    wl = W.Workload("t", sp, W.Link(W.make_spans([50.0], cr=0.0)), W.Numerics(n_grid=24, egn=0), np.array([2]))
+    t = oracle.square_terms(wl, 2, 2, 2, method="segment")
+    assert (t[0, 0] > 0 and t[2, 0] > 0) == expect_side
+    assert t[1, 0] > 0
+
+
+def test_island_terms_symmetry():
+    """D(k1,k2,l) = D(k2,k1,l) and E(k1,k2,l) = F(k2,k1,l) for the bare integrals."""
+    wl = W.small_mixed(n_ch=6, n_spans=2, n_grid=12)
+    for k1, k2 in [(0, 3), (1, 2), (2, 5)]:
+        a = oracle.square_terms(wl, 2, k1, k2, method="integral")
+        b = oracle.square_terms(wl, 2, k2, k1, method="integral")
+        assert np.allclose(a[:, 0], b[:, 0], rtol=1e-13, atol=0)
+        assert np.allclose(a[:, 1], b[:, 2], rtol=1e-13, atol=0)
+        assert np.allclose(a[:, 3], b[:, 3], rtol=1e-13, atol=0)
+        assert np.allclose(a[:, 4], b[:, 4], rtol=1e-13, atol=0)
+
+
+def _literal_terms(wl, cut, k1, k2, l, method="segment"):
+    """Eqs. 17-21 written out literally on the N x N midpoint grid, including the
+    second inner integrals, for tiny N (O(N^4) work).  Uses only the oracle's
+    Upsilon and S."""
+    sp = wl.spectrum
+    N = wl.numerics.n_grid
+    rs, ro, df = sp.symbol_rate_thz, sp.rolloff, sp.spacing_thz
+    Wd = (1 + ro) * rs
+    h = Wd / N
+    nu = lambda k: (k - (sp.n_ch - 1) / 2) * df
+    spans = wl.link.spans
+    ptot = sp.power_w.sum()
+    B = sp.n_ch * df
+    fs = -Wd / 2 + (np.arange(N) + 0.5) * h
+    U = np.zeros((N, N), complex)
+    for i in range(N):
+        for j in range(N):
+            U[i, j] = oracle.upsilon(spans, ptot, B, nu(k1) + fs[i], nu(k2) + fs[j], nu(cut), method)
+    S = np.array([oracle.S(x, rs, ro) for x in fs])
+
+    def S3(i, j):
+        f3 = fs[i] + fs[j] - l * df
+        return oracle.S(f3, rs, ro) if abs(f3) <= Wd / 2 else 0.0
+
+    S3m = np.array([[S3(i, j) for j in range(N)] for i in range(N)])
+    D = h * h * np.sum(S[:, None] ** 2 * S[None, :] ** 2 * S3m ** 2 * np.abs(U) ** 2)
+    # Eq. 18: int df2 |S2|^2 int df1 S1 S3 U  int df1' S1' S3' U'^*
+    E = 0.0
+    for j in range(N):
+        for i in range(N):
+            for ip in range(N):
+                E += h ** 3 * S[j] ** 2 * S[i] * S3m[i, j] * U[i, j] * S[ip] * S3m[ip, j] * np.conj(U[ip, j])
+    # Eq. 19: int df1 |S1|^2 int df2 S2 S3 U int df2' S2' S3' U'^*
+    F = 0.0
+    for i in range(N):
+        for j in range(N):
+            for jp in range(N):
+                F += h ** 3 * S[i] ** 2 * S[j] * S3m[i, j] * U[i, j] * S[jp] * S3m[i, jp] * np.conj(U[i, jp])
+    # Eq. 20: int df1 int df2 S1 S2 |S3|^2 U int df1' S1' S(f1+f2-f1') U^*(f1', f1+f2-f1')
+    G = 0.0
+    for i in range(N):
+        for j in range(N):
+            for ip in range(N):
+                jp = i + j - ip
+                if 0 <= jp < N:
+                    G += h ** 3 * S[i] * S[j] * S3m[i, j] ** 2 * U[i, j] * S[ip] * S[jp] * np.conj(U[ip, jp])
+    # Eq. 21: the full double sum times its conjugate
+    tot = h * h * np.sum(S[:, None] * S[None, :] * S3m * U)
+    H = abs(tot) ** 2
+    return np.array([D, E.real, F.real, G.real, H])
+
+
+@pytest.mark.parametrize("k1,k2,l", [(1, 3, 0), (2, 2, 0), (3, 2, -1), (2, 1, 1), (0, 2, 0)])
+def test_island_terms_match_literal_equations(k1, k2, l):
+    """The restructured row / column / anti-diagonal / full sums equal the
+    literal four- and five-fold integrals of Eqs. 17-21 on the same grid."""
+    wl = W.small_mixed(n_ch=5, n_spans=2, n_grid=8, rolloff=0.3, rs=0.07)
+    cut = 2
+    lit = _literal_terms(wl, cut, k1, k2, l)
+    got = oracle.square_terms(wl, cut, k1, k2, method="segment")[l + 1]
+    assert np.allclose(got, lit, rtol=1e-10, atol=1e-30 + 1e-12 * abs(lit[0])), (got, lit)
+
+
+def test_grid_rule_converges_to_dense_cubature():
+    """One channel, one span: the midpoint grid converges at second order to an
+    adaptive 2-D cubature of the continuous SCI integrand (Eq. 17)."""
+    sp = W.spectrum_from(1, 0.05, 0.032, 0.2, [1e-3], ["gaussian"])
+    wl = W.Workload("t", sp, W.Link(W.make_spans([40.0], cr=0.0, beta2=-21.7, beta3=0.0)),
+                    W.Numerics(n_grid=8, egn=0), np.array([0]))
+    rs, ro = 0.032, 0.2
+    Wd = (1 + ro) * rs
+    spans = wl.link.spans
+
+    def integrand(f2, f1):
+        f3 = f1 + f2
+        if abs(f3) > Wd / 2:
+            return 0.0
+        u = oracle.upsilon(spans, 1e-3, 0.05, f1, f2, 0.0, "segment")
+        return (oracle.S(f1, rs, ro) * oracle.S(f2, rs, ro) * oracle.S(f3, rs, ro)) ** 2 * abs(u) ** 2
+
+    ref, _ = si.dblquad(integrand, -Wd / 2, Wd / 2, -Wd / 2, Wd / 2, epsabs=0, epsrel=1e-8)
+    errs = []
+    for N in (16, 32, 64):
+        t = oracle.square_terms(wl, 0, 0, 0, method="segment", n_grid=N)
+        errs.append(abs(t[1, 0] - ref) / ref)
+    assert errs[-1] < 2e-3
+    assert errs[0] / errs[1] > 2.5 and errs[1] / errs[2] > 2.5, errs
+
+
+def test_gaussian_formats_give_gn():
+    wl = W.small_mixed(n_ch=5, n_spans=2, n_grid=10)
+    wl.spectrum.phi[:] = 0.0
+    wl.spectrum.psi[:] = 0.0
+    a = oracle.eval_cuts(wl, cuts=[2], method="segment")
+    b = oracle.eval_cuts(wl.with_numerics(egn=0), cuts=[2], method="segment")
+    assert a["sigma2"][0] == b["sigma2"][0]
+    assert np.all(a["terms"][0, 1:] == 0)
+
+
+def test_e_and_f_contributions_balance():
+    """By f1 <-> f2 symmetry the E and F sums over T_kappa carry equal bare
+    weight, so swapping the 16/27 and 32/81 prefactors changes nothing."""
+    wl = W.small_mixed(n_ch=5, n_spans=2, n_grid=10)
+    r = oracle.eval_cuts(wl, cuts=[1, 2], method="segment")
+    for t in r["terms"]:
+        assert abs(t[1] / (16 / 27) - t[2] / (32 / 81)) <= 1e-12 * abs(t[1] / (16 / 27))
+
+
+def test_cubic_power_scaling():
+    """sigma^2 scales as P^3 with the ISRS profile frozen; eta is invariant."""
+    wl = W.small_mixed(n_ch=5, n_spans=2, n_grid=10)
+    wl.link.ptot_override_w = 0.05
+    r1 = oracle.eval_cuts(wl, cuts=[2], method="integral")
+    wl.spectrum.power_w *= 3.0
+    r3 = oracle.eval_cuts(wl, cuts=[2], method="integral")
+    assert abs(r3["sigma2"][0] / r1["sigma2"][0] - 27.0) < 1e-10 * 27
+    assert abs(r3["eta"][0] / r1["eta"][0] - 1.0) < 1e-10
+
+
+def test_cr_continuity_at_zero():
+    wl = W.small_mixed(n_ch=5, n_spans=2, n_grid=10)
+    wl.link.spans["cr_w_km_thz"] = 0.0
+    a = oracle.eval_cuts(wl, cuts=[2], method="integral")["eta"][0]
+    wl.link.spans["cr_w_km_thz"] = 1e-9
+    b = oracle.eval_cuts(wl, cuts=[2], method="integral")["eta"][0]
+    assert abs(a - b) <= 1e-9 * a
+
+
+def test_format_constants_from_constellations():
+    g = _golden("egn_format_constants.json")
+
+    def qam(m):
+        k = int(round(math.sqrt(m)))
+        lv = np.arange(-(k - 1), k, 2, dtype=float)
+        return (lv[:, None] + 1j * lv[None, :]).ravel()
+
+    const = {"qpsk": qam(4), "16qam": qam(16), "64qam": qam(64)}
+    for c in g["cases"]:
+        phi, psi = oracle.format_constants(const[c["format"]])
+        assert abs(phi - c["phi"]) <= c["tol"]
+        if "psi" in c:
+            assert abs(psi - c["psi"]) <= c["tol"]
+    # The workload table carries the oracle's values.
+    for name, pts in const.items():
+        phi, psi = oracle.format_constants(pts)
+        assert abs(W.FORMATS[name][0] - phi) < 1e-12 and abs(W.FORMATS[name][1] - psi) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# Paper-level accuracy of the closed forms (loose, Sec. III-C)
+# --------------------------------------------------------------------------
+
+@pytest.mark.slow
+def test_closed_form_errors_match_paper_magnitudes():
+    g = _golden("paper_accuracy.json")
+    cuts = [50, 25, 0]
+    res = {}
+    for cr in (0.28, 1.12):
+        wl = W.table1_1thz(cr=cr, fmt="qpsk", n_grid=10)
+        ref = oracle.eval_cuts(wl, cuts=cuts, method="integral")["eta"]
+        seg = oracle.eval_cuts(wl, cuts=cuts, method="segment")["eta"]
+        mac = oracle.eval_cuts(wl, cuts=cuts, method="maclaurin")["eta"]
+        res[cr] = (10 * np.log10(seg / ref), 10 * np.log10(mac / ref))
+    seg112, mac112 = res[1.12]
+    seg028, mac028 = res[0.28]
+    # segment: at most a few thousandths of a dB even at strong ISRS
+    assert np.max(np.abs(seg112)) < 2.5 * g["segment_max_abs_err_db_cr112"]
+    assert np.mean(np.abs(np.concatenate([seg112, seg028]))) < 2 * g["segment_mae_db_bound"]
+    # Maclaurin: about a hundredth of a dB at Cr 0.28, tenths of a dB at 1.12
+    lo, hi = g["maclaurin_err_range_db_cr028"]
+    assert np.max(np.abs(mac028)) < 2.0 * max(abs(lo), abs(hi))
+    m = np.max(np.abs(mac112))
+    assert 0.25 * g["maclaurin_max_abs_err_db_cr112"] < m < 2.0 * g["maclaurin_max_abs_err_db_cr112"]
+    assert np.max(np.abs(mac112)) > 10 * np.max(np.abs(seg112))
