@@ -1,0 +1,190 @@
+/*
+ * isrs_egn.h -- C-ABI of the MI355X (gfx950) ISRS-aware EGN library.
+ *
+ * The library evaluates, per channel under test (CUT), the nonlinear
+ * interference (NLI) of a WDM link with inter-channel stimulated Raman
+ * scattering (ISRS) as in "Acceleration and Parallelization Methods for ISRS
+ * EGN Model" (arXiv 2412.11614):
+ *   - the NLI variance sigma^2 (Eq. 15) summed over the islands of the set
+ *     T_kappa (Eq. 16), with the GN term D (Eq. 17) and the modulation-format
+ *     terms E, F, G, H (Eqs. 18-21);
+ *   - the link function Upsilon (Eq. 22), whose per-span FWM efficiency
+ *     factor mu_s (Eq. 23) is taken from the segment closed form (Eqs. 7-10),
+ *     or, on request, the Maclaurin closed form (Eqs. 2-6);
+ *   - the NLI coefficient eta = sigma^2 / P^3 (Eq. 11) and the NLI PSD.
+ *
+ * Conventions shared by every call
+ *   Units: frequencies THz, lengths km, powers W, alpha dB/km, beta2 ps^2/km,
+ *   beta3 ps^3/km, gamma 1/(W km), Raman gain slope Cr 1/(W km THz).
+ *   Channel k of an n_ch grid sits at (k - (n_ch-1)/2) * spacing from the
+ *   grid centre; the ISRS profile (Eq. 25) uses that origin, B_tot =
+ *   n_ch * spacing and P_tot = sum of the launch powers.  |S(f)|^2 is the
+ *   raised-cosine shape divided by Rs^2.  Each channel-pair square is an
+ *   N x N midpoint grid over the channel's spectral support; a point belongs
+ *   to island l when |f1 + f2 - f - l*spacing| <= (1+rolloff) Rs / 2.
+ *
+ *   Every call returns an isrs_status: ISRS_OK (0) or a negative code.
+ *   Inputs are validated before any device work; on error nothing is
+ *   launched and isrs_last_error() describes the first problem found.
+ *   Pointers documented as "host" are read or written by the CPU during
+ *   the call; "device" pointers must be device memory of the context's GPU.
+ *   The library copies what it needs: callers keep ownership of every
+ *   buffer they pass.  No call throws across the boundary.
+ *
+ *   A context owns a HIP stream (borrowed or default) and device scratch
+ *   that it grows on demand and frees in isrs_destroy.  Use one context per
+ *   host thread; calls on one context must not overlap.
+ */
+#ifndef ISRS_EGN_H
+#define ISRS_EGN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define ISRS_OK 0
+#define ISRS_E_ARG (-1)       /* bad argument: null pointer, size, numerics, CUT index */
+#define ISRS_E_SPECTRUM (-2)  /* bad spectrum: non-finite, negative power, (1+ro)Rs > spacing, ... */
+#define ISRS_E_LINK (-3)      /* bad span list: non-positive length or loss, non-finite values */
+#define ISRS_E_STATE (-4)     /* evaluation before isrs_set_spectrum / isrs_set_link */
+#define ISRS_E_DEVICE (-5)    /* no usable gfx950 device, or a HIP runtime error */
+#define ISRS_E_NOMEM (-6)     /* device or host allocation failed */
+#define ISRS_E_NUMERIC (-7)   /* a result came out non-finite */
+
+/* Amplifier gain reading for the products of Eq. 22. */
+#define ISRS_GAIN_EQUALIZED 0 /* gain restores the launch profile: all products are 1 */
+#define ISRS_GAIN_LOSS_ONLY 1 /* g_s = exp(alpha_s L_s): products taken literally */
+
+/* Arithmetic of the per-point integrand. */
+#define ISRS_PREC_FP64 0         /* everything in FP64 */
+#define ISRS_PREC_FP32_PHASE64 1 /* phases reduced in FP64, integrand in FP32, sums in FP64 */
+
+/* FWM efficiency factor per span. */
+#define ISRS_MU_SEGMENT 0   /* segment closed form, Eqs. 7-10 */
+#define ISRS_MU_MACLAURIN 1 /* Maclaurin closed form, Eqs. 2-6 */
+
+typedef struct isrs_ctx isrs_ctx;
+
+/* WDM spectrum (the problem statement of Sec. II-B; P, Phi, Psi of Eq. 15).
+ * power_w[k] = 0 marks an empty slot.  phi/psi are the format constants of
+ * the EGN correction terms (e.g. QPSK -1 / 4, Gaussian 0 / 0).  All arrays
+ * are host arrays of n_ch doubles, copied by isrs_set_spectrum. */
+typedef struct {
+    int32_t n_ch;
+    double f_center_thz;     /* informational: absolute grid centre */
+    double spacing_thz;      /* channel spacing */
+    double symbol_rate_thz;  /* Rs */
+    double rolloff;          /* raised-cosine roll-off in [0, 1] */
+    const double* power_w;   /* [n_ch] launch power per channel, W */
+    const double* phi;       /* [n_ch] */
+    const double* psi;       /* [n_ch] */
+} isrs_spectrum;
+
+/* One fibre span (parameters of Eqs. 22-25). */
+typedef struct {
+    double length_km;
+    double alpha_db_km;
+    double beta2_ps2_km;
+    double beta3_ps3_km;
+    double gamma_w_km;
+    double cr_w_km_thz;
+} isrs_span;
+
+/* Discretisation and arithmetic.  n1 == n2 = N is the grid per square;
+ * n_f outer samples of f over [-Rs/2, Rs/2] (1: the CUT centre, then
+ * sigma^2 = Rs * PSD(0)); K_s = ceil(L_s / dz_km) segments per span
+ * (Eq. 7-10, Sec. II-C); egn = 0 keeps only the GN term D. */
+typedef struct {
+    double dz_km;
+    int32_t n1, n2, n_f;
+    int32_t egn;
+    int32_t precision;  /* ISRS_PREC_* */
+    int32_t mu_method;  /* ISRS_MU_* */
+} isrs_numerics;
+
+/* Counters and timings of the last evaluation on a context. */
+typedef struct {
+    double region_ms;       /* summed duration of the region-kernel launches (HIP events) */
+    double egn_ms;          /* summed duration of the EGN-sum launches */
+    double assemble_ms;     /* per-CUT assembly launch */
+    double host_prep_ms;    /* host-side tables and work list */
+    int64_t region_launches;
+    int64_t n_squares;      /* channel-pair squares evaluated (f1<->f2 folded) */
+    int64_t n_delta_squares;/* squares needing the E/F/G/H coherent sums */
+    int64_t n_points_live;  /* grid points on live islands, folded squares */
+    int64_t horner_steps;   /* sum over live points and spans of K_s */
+    double alg_flop;        /* algorithmic FLOP: sum over live point-spans of 8 K_s + 30 */
+} isrs_stats;
+
+/* Context lifetime.  device: HIP device ordinal; hip_stream: a hipStream_t
+ * to order all work on, or NULL for the library's own stream.  Fails with
+ * ISRS_E_DEVICE when the device is absent or not gfx950. */
+int32_t isrs_create(isrs_ctx** out, int32_t device, void* hip_stream);
+int32_t isrs_destroy(isrs_ctx* ctx);
+
+/* Message of the last failure on ctx ("" if none).  ctx may be NULL, then
+ * the message of the last failed isrs_create on this thread. */
+const char* isrs_last_error(const isrs_ctx* ctx);
+
+/* Deep-copies the spectrum (Sec. II-B problem statement; P, Phi, Psi of
+ * Eq. 15).  Errors: ISRS_E_ARG (null), ISRS_E_SPECTRUM (invalid values). */
+int32_t isrs_set_spectrum(isrs_ctx* ctx, const isrs_spectrum* spectrum);
+
+/* Deep-copies n_spans spans (Eqs. 22-25) and the gain reading.
+ * Errors: ISRS_E_ARG, ISRS_E_LINK. */
+int32_t isrs_set_link(isrs_ctx* ctx, const isrs_span* spans, int32_t n_spans, int32_t gain_mode);
+
+/* Freezes P_tot of the ISRS profile (Eq. 25) at ptot_w (> 0), or restores
+ * the sum of launch powers (ptot_w = 0). */
+int32_t isrs_set_ptot_override(isrs_ctx* ctx, double ptot_w);
+
+/* NLI coefficient per CUT, Eq. 11 (and sigma^2 of Eq. 15).
+ * cuts: host [n_cut] channel indices (active channels).
+ * eta: host [n_cut] 1/W^2; sigma2: host [n_cut] W or NULL; terms: host
+ * [n_cut*5] or NULL, the D, E, F, G, H contributions to sigma^2 (they sum
+ * to sigma^2).  Synchronises the stream before returning.
+ * Errors: ISRS_E_ARG, ISRS_E_STATE, ISRS_E_DEVICE, ISRS_E_NOMEM, ISRS_E_NUMERIC. */
+int32_t isrs_eval_eta(isrs_ctx* ctx, const isrs_numerics* numerics, const int32_t* cuts, int32_t n_cut,
+                      double* eta, double* sigma2, double* terms);
+
+/* As isrs_eval_eta with device outputs (eta_dev [n_cut], sigma2_dev and
+ * terms_dev nullable); stream-ordered, does not synchronise and does not
+ * check results for finiteness.  cuts stays a host array. */
+int32_t isrs_eval_eta_dev(isrs_ctx* ctx, const isrs_numerics* numerics, const int32_t* cuts, int32_t n_cut,
+                          double* eta_dev, double* sigma2_dev, double* terms_dev);
+
+/* NLI PSD at the n_f outer samples of each CUT (Eq. 15 without the outer
+ * integral over f): f_thz host [n_cut*n_f] offsets from the CUT centre,
+ * psd host [n_cut*n_f] in W/THz.  sigma^2 = sum_f (Rs/n_f) psd. */
+int32_t isrs_eval_psd(isrs_ctx* ctx, const isrs_numerics* numerics, const int32_t* cuts, int32_t n_cut,
+                      double* f_thz, double* psd_w_per_thz);
+
+/* Island-level values for checking: for CUT `cut` and m squares
+ * kappa12 = host [m*2] (k1, k2) pairs, writes host partials[m*15]: for
+ * l = -1, 0, 1 the bare integrals D, E, F, G, H of Eqs. 17-21 at f = 0
+ * (no R^n prefactors, constants, powers or format factors).  Islands whose
+ * third channel is outside the grid or inactive are 0. */
+int32_t isrs_eval_islands(isrs_ctx* ctx, const isrs_numerics* numerics, int32_t cut,
+                          const int32_t* kappa12, int32_t m, double* partials);
+
+/* Counters of the last evaluation; set profile = 1 to time each launch
+ * with HIP events (adds a small host overhead per launch). */
+int32_t isrs_set_profiling(isrs_ctx* ctx, int32_t profile);
+int32_t isrs_get_stats(const isrs_ctx* ctx, isrs_stats* out);
+
+/* Pure host checks used by the set/eval calls (no device needed). */
+int32_t isrs_validate_spectrum(const isrs_spectrum* spectrum);
+int32_t isrs_validate_link(const isrs_span* spans, int32_t n_spans, int32_t gain_mode);
+int32_t isrs_validate_numerics(const isrs_numerics* numerics);
+
+/* Library version string. */
+const char* isrs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ISRS_EGN_H */

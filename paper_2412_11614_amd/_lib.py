@@ -1,0 +1,283 @@
+"""ctypes binding of libisrs_egn.so (argument marshalling only).
+
+Every step of the computation runs in the HIP library; this module converts
+numpy arrays and torch device tensors into the plain pointers and structs of
+include/isrs_egn.h.  It raises when the library is missing: there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libisrs_egn.so")
+
+ISRS_OK = 0
+ISRS_E_ARG = -1
+ISRS_E_SPECTRUM = -2
+ISRS_E_LINK = -3
+ISRS_E_STATE = -4
+ISRS_E_DEVICE = -5
+ISRS_E_NOMEM = -6
+ISRS_E_NUMERIC = -7
+
+STATUS_NAMES = {0: "ISRS_OK", -1: "ISRS_E_ARG", -2: "ISRS_E_SPECTRUM", -3: "ISRS_E_LINK",
+                -4: "ISRS_E_STATE", -5: "ISRS_E_DEVICE", -6: "ISRS_E_NOMEM", -7: "ISRS_E_NUMERIC"}
+
+EXPORTED = [
+    "isrs_create", "isrs_destroy", "isrs_last_error", "isrs_set_spectrum", "isrs_set_link",
+    "isrs_set_ptot_override", "isrs_eval_eta", "isrs_eval_eta_dev", "isrs_eval_psd",
+    "isrs_eval_islands", "isrs_set_profiling", "isrs_get_stats", "isrs_validate_spectrum",
+    "isrs_validate_link", "isrs_validate_numerics", "isrs_version",
+]
+
+
+class IsrsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Spectrum_c(C.Structure):
+    _fields_ = [("n_ch", C.c_int32), ("f_center_thz", C.c_double), ("spacing_thz", C.c_double),
+                ("symbol_rate_thz", C.c_double), ("rolloff", C.c_double),
+                ("power_w", C.POINTER(C.c_double)), ("phi", C.POINTER(C.c_double)),
+                ("psi", C.POINTER(C.c_double))]
+
+
+class Span_c(C.Structure):
+    _fields_ = [("length_km", C.c_double), ("alpha_db_km", C.c_double), ("beta2_ps2_km", C.c_double),
+                ("beta3_ps3_km", C.c_double), ("gamma_w_km", C.c_double), ("cr_w_km_thz", C.c_double)]
+
+
+class Numerics_c(C.Structure):
+    _fields_ = [("dz_km", C.c_double), ("n1", C.c_int32), ("n2", C.c_int32), ("n_f", C.c_int32),
+                ("egn", C.c_int32), ("precision", C.c_int32), ("mu_method", C.c_int32)]
+
+
+class Stats_c(C.Structure):
+    _fields_ = [("region_ms", C.c_double), ("egn_ms", C.c_double), ("assemble_ms", C.c_double),
+                ("host_prep_ms", C.c_double), ("region_launches", C.c_int64), ("n_squares", C.c_int64),
+                ("n_delta_squares", C.c_int64), ("n_points_live", C.c_int64), ("horner_steps", C.c_int64),
+                ("alg_flop", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2412_11614_amd.build "
+                           "(there is no CPU fallback)")
+    L = C.CDLL(LIB_PATH)
+    vp = C.c_void_p
+    dp = C.POINTER(C.c_double)
+    ip = C.POINTER(C.c_int32)
+    L.isrs_create.argtypes = [C.POINTER(vp), C.c_int32, vp]
+    L.isrs_destroy.argtypes = [vp]
+    L.isrs_last_error.argtypes = [vp]
+    L.isrs_last_error.restype = C.c_char_p
+    L.isrs_set_spectrum.argtypes = [vp, C.POINTER(Spectrum_c)]
+    L.isrs_set_link.argtypes = [vp, C.POINTER(Span_c), C.c_int32, C.c_int32]
+    L.isrs_set_ptot_override.argtypes = [vp, C.c_double]
+    L.isrs_eval_eta.argtypes = [vp, C.POINTER(Numerics_c), ip, C.c_int32, dp, dp, dp]
+    L.isrs_eval_eta_dev.argtypes = [vp, C.POINTER(Numerics_c), ip, C.c_int32, vp, vp, vp]
+    L.isrs_eval_psd.argtypes = [vp, C.POINTER(Numerics_c), ip, C.c_int32, dp, dp]
+    L.isrs_eval_islands.argtypes = [vp, C.POINTER(Numerics_c), C.c_int32, ip, C.c_int32, dp]
+    L.isrs_set_profiling.argtypes = [vp, C.c_int32]
+    L.isrs_get_stats.argtypes = [vp, C.POINTER(Stats_c)]
+    L.isrs_validate_spectrum.argtypes = [C.POINTER(Spectrum_c)]
+    L.isrs_validate_link.argtypes = [C.POINTER(Span_c), C.c_int32, C.c_int32]
+    L.isrs_validate_numerics.argtypes = [C.POINTER(Numerics_c)]
+    L.isrs_version.argtypes = []
+    L.isrs_version.restype = C.c_char_p
+    for name in EXPORTED:
+        f = getattr(L, name)
+        if f.restype is C.c_int:  # default
+            f.restype = C.c_int32
+    _lib = L
+    return L
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+class _SpectrumArgs:
+    def __init__(self, spectrum):
+        self.p = _f64(spectrum.power_w)
+        self.phi = _f64(spectrum.phi)
+        self.psi = _f64(spectrum.psi)
+        self.c = Spectrum_c(int(spectrum.n_ch), float(getattr(spectrum, "f_center_thz", 193.4)),
+                            float(spectrum.spacing_thz), float(spectrum.symbol_rate_thz),
+                            float(spectrum.rolloff), _dp(self.p), _dp(self.phi), _dp(self.psi))
+
+
+def span_structs(spans):
+    """Structured span records (or an [n, 6] array) -> ctypes array of Span_c."""
+    if getattr(spans, "dtype", None) is not None and spans.dtype.names:
+        cols = ["length_km", "alpha_db_km", "beta2_ps2_km", "beta3_ps3_km", "gamma_w_km", "cr_w_km_thz"]
+        arr = np.stack([np.asarray(spans[c], np.float64) for c in cols], axis=1)
+    else:
+        arr = _f64(spans).reshape(-1, 6)
+    out = (Span_c * arr.shape[0])()
+    for i, row in enumerate(arr):
+        out[i] = Span_c(*[float(x) for x in row])
+    return out
+
+
+def numerics_struct(numerics, **override):
+    d = dict(n=int(numerics.n_grid), n_f=int(numerics.n_f), dz=float(numerics.dz_km),
+             egn=int(numerics.egn), precision=int(numerics.precision),
+             mu_method=int(getattr(numerics, "mu_method", 0)))
+    d.update(override)
+    return Numerics_c(d["dz"], d["n"], d["n"], d["n_f"], d["egn"], d["precision"], d["mu_method"])
+
+
+def validate_spectrum(spectrum):
+    a = _SpectrumArgs(spectrum)
+    return lib().isrs_validate_spectrum(C.byref(a.c))
+
+
+def validate_link(spans, gain_mode=0):
+    s = span_structs(spans)
+    return lib().isrs_validate_link(s, len(s), int(gain_mode))
+
+
+def validate_numerics(numerics):
+    n = numerics if isinstance(numerics, Numerics_c) else numerics_struct(numerics)
+    return lib().isrs_validate_numerics(C.byref(n))
+
+
+@dataclass
+class Stats:
+    region_ms: float
+    egn_ms: float
+    assemble_ms: float
+    host_prep_ms: float
+    region_launches: int
+    n_squares: int
+    n_delta_squares: int
+    n_points_live: int
+    horner_steps: int
+    alg_flop: float
+
+
+class Engine:
+    """One library context on one GPU.  Mirrors the C-ABI calls."""
+
+    def __init__(self, device: int = 0, stream=None):
+        L = lib()
+        self._h = C.c_void_p()
+        s = C.c_void_p(int(stream)) if stream is not None else None
+        rc = L.isrs_create(C.byref(self._h), int(device), s)
+        if rc != ISRS_OK:
+            raise IsrsError(rc, L.isrs_last_error(None).decode())
+        self._L = L
+
+    def close(self):
+        if self._h:
+            self._L.isrs_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, rc):
+        if rc != ISRS_OK:
+            raise IsrsError(rc, self._L.isrs_last_error(self._h).decode())
+
+    def set_spectrum(self, spectrum):
+        a = _SpectrumArgs(spectrum)
+        self._check(self._L.isrs_set_spectrum(self._h, C.byref(a.c)))
+
+    def set_link(self, spans, gain_mode=0):
+        s = span_structs(spans)
+        self._check(self._L.isrs_set_link(self._h, s, len(s), int(gain_mode)))
+
+    def set_ptot_override(self, w):
+        self._check(self._L.isrs_set_ptot_override(self._h, float(w)))
+
+    def set_profiling(self, on=True):
+        self._check(self._L.isrs_set_profiling(self._h, 1 if on else 0))
+
+    def load(self, workload):
+        """set_spectrum + set_link (+ ptot override) from a workloads.Workload."""
+        self.set_spectrum(workload.spectrum)
+        self.set_link(workload.link.spans, workload.link.gain_mode)
+        self.set_ptot_override(workload.link.ptot_override_w)
+
+    def eval_eta(self, numerics, cuts, **override):
+        nu = numerics if isinstance(numerics, Numerics_c) else numerics_struct(numerics, **override)
+        cuts = np.ascontiguousarray(np.asarray(cuts, dtype=np.int32))
+        n = len(cuts)
+        eta = np.zeros(n)
+        s2 = np.zeros(n)
+        terms = np.zeros((n, 5))
+        self._check(self._L.isrs_eval_eta(self._h, C.byref(nu), _ip(cuts), n, _dp(eta), _dp(s2), _dp(terms)))
+        return {"eta": eta, "sigma2": s2, "terms": terms}
+
+    def eval_eta_dev(self, numerics, cuts, eta_dev, sigma2_dev=None, terms_dev=None, **override):
+        """Device outputs (torch tensors of float64 on the context's GPU); stream-ordered."""
+        nu = numerics if isinstance(numerics, Numerics_c) else numerics_struct(numerics, **override)
+        cuts = np.ascontiguousarray(np.asarray(cuts, dtype=np.int32))
+        ptr = lambda t: None if t is None else C.c_void_p(t.data_ptr())
+        for t in (eta_dev, sigma2_dev, terms_dev):
+            if t is not None and (str(t.dtype) != "torch.float64" or not t.is_cuda or not t.is_contiguous()):
+                raise ValueError("device outputs must be contiguous float64 GPU tensors")
+        if eta_dev.numel() < len(cuts):
+            raise ValueError("eta_dev too small")
+        if sigma2_dev is not None and sigma2_dev.numel() < len(cuts):
+            raise ValueError("sigma2_dev too small")
+        if terms_dev is not None and terms_dev.numel() < 5 * len(cuts):
+            raise ValueError("terms_dev too small")
+        self._check(self._L.isrs_eval_eta_dev(self._h, C.byref(nu), _ip(cuts), len(cuts), ptr(eta_dev),
+                                              ptr(sigma2_dev), ptr(terms_dev)))
+
+    def eval_psd(self, numerics, cuts, **override):
+        nu = numerics if isinstance(numerics, Numerics_c) else numerics_struct(numerics, **override)
+        cuts = np.ascontiguousarray(np.asarray(cuts, dtype=np.int32))
+        n = len(cuts)
+        f = np.zeros((n, nu.n_f))
+        psd = np.zeros((n, nu.n_f))
+        self._check(self._L.isrs_eval_psd(self._h, C.byref(nu), _ip(cuts), n, _dp(f), _dp(psd)))
+        return f, psd
+
+    def eval_islands(self, numerics, cut, squares, **override):
+        """Bare D, E, F, G, H per island: array [m, 3 (l = -1, 0, 1), 5]."""
+        nu = numerics if isinstance(numerics, Numerics_c) else numerics_struct(numerics, **override)
+        sq = np.ascontiguousarray(np.asarray(squares, dtype=np.int32).reshape(-1, 2))
+        m = sq.shape[0]
+        out = np.zeros(m * 15)
+        self._check(self._L.isrs_eval_islands(self._h, C.byref(nu), int(cut), _ip(sq), m, _dp(out)))
+        return out.reshape(m, 3, 5)
+
+    def stats(self) -> Stats:
+        s = Stats_c()
+        self._check(self._L.isrs_get_stats(self._h, C.byref(s)))
+        return Stats(*[getattr(s, f[0]) for f in Stats_c._fields_])

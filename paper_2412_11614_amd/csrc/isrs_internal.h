@@ -1,0 +1,130 @@
+// isrs_internal.h -- device-side data layout shared by the host layer
+// (isrs_api.cpp) and the gfx950 kernels (isrs_kernels.hip).  Not installed;
+// the public interface is include/isrs_egn.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace isrs {
+
+// Region tile: TILE x TILE grid points per pass, 256 threads, each thread
+// owns 4 points of one tile column (rows r0, r0+8, r0+16, r0+24).
+constexpr int TILE = 32;
+constexpr int THREADS = 256;
+constexpr int PPT = 4;                // points per thread per tile
+constexpr int NAD = 2 * TILE - 1;     // anti-diagonals crossing a tile
+constexpr int STAGE_RUN = 16;         // anti-diagonals per staging run (one exp, then a recurrence)
+
+// Per-span constants, all FP64.  The phase of the segment step, Eq. 9, is
+// chi * Delta with chi of Eq. 24; the accumulated phase of Eq. 22 is Theta_s.
+// Both are formed in revolutions from d12 = (f1-f)(f2-f) and s = f1 + f2:
+//   chi Delta / 2pi = d12 (c2r + c3r s),   Theta_s / 2pi = d12 (p2r + p3r s),
+//   chi = d12 (c2x + c3x s)  [rad/km].
+struct SpanConst {
+    double c2r, c3r;       // 2 pi beta2 Delta,  2 pi^2 beta3 Delta
+    double c2x, c3x;       // 4 pi^2 beta2,      4 pi^3 beta3
+    double p2r, p3r;       // 2 pi sum_{s'<s} beta2 L,  2 pi^2 sum_{s'<s} beta3 L
+    double c2L, c3L;       // 2 pi beta2 L,  2 pi^2 beta3 L  (Maclaurin form)
+    double em;             // exp(-alpha Delta)
+    double emL, em2L;      // exp(-alpha L), exp(-2 alpha L)
+    double alpha;          // 1/km
+    double gamma;          // 1/(W km)
+    double pcr;            // Ptot Cr (Maclaurin form), 1/(km THz)
+    double pi_a, pi_s, pi_c;  // LOSS_ONLY gain: ln Pi_s = pi_a - pi_s (a+b) + pi_c c
+    int K;                 // segments
+    int off;               // offset of the span's rows in the segment tables
+};
+
+// Segment table row k of a span: SRS gain at z_k = A exp(-zeta f3abs)
+// (Eq. 8 with Eq. 10) and the step ratio exp(-zeta h) between neighbouring
+// anti-diagonals of the grid.
+struct SegRow64 {
+    double A, zeta, ratio, pad;
+};
+struct SegRow32 {
+    float A, zeta, ratio, pad;
+};
+
+// One (CUT, outer-frequency) instance.
+struct InstDesc {
+    double f;        // outer frequency offset from the CUT centre, THz
+    int cut;         // channel index
+    int nf_idx;      // outer-frequency sample -> island tables
+    int sq_begin;    // its squares in the work list
+    int sq_end;
+};
+
+// One channel-pair square of the (f1 <-> f2 folded) work list.
+struct SquareItem {
+    int inst;
+    int k1, k2;
+    int lmask;       // bit (l+1): island l has a valid third channel and live points
+    int egn_mask;    // bit 4*(l+1) + t, t = 0 E (rows), 1 F (columns), 2 G (anti-diagonals), 3 H (full)
+    int y_slot;      // slot in the chunk's Upsilon buffer, -1 if no coherent sums are needed
+    int d_index;     // row in the coherent-sum results, -1 if none
+    float mult;      // 2 for k1 < k2 (mirror square folded in), else 1
+};
+
+struct RegionArgs {
+    const SpanConst* spans;
+    const void* seg;          // SegRow32 or SegRow64 rows
+    const double* Sg;         // [N] S(f) at the grid points
+    const double* wt;         // [n_f][3][2N-1] island weight per anti-diagonal (1, 1/2 on a tie, 0)
+    const double* s3;         // [n_f][3][2N-1] S(f3) per anti-diagonal
+    const int* livep;         // [n_f][3][2N] prefix counts of live anti-diagonals
+    const InstDesc* insts;
+    const SquareItem* items;
+    double* partD;            // [n_items][n_groups][3]
+    void* ybuf;               // Upsilon of the chunk's coherent-sum squares, [slot][N][N] complex
+    int item0;                // first item of this chunk
+    int n_groups;             // strip groups per square
+    int spb;                  // tile strips per group
+    int nt;                   // tiles per side
+    int N;
+    int n_ch;
+    int n_sp;
+    int gain_mode;
+    int mu_method;
+    double h;                 // grid step, THz
+    double spacing;           // channel spacing, THz
+};
+
+struct EgnArgs {
+    const double* Sg;
+    const double* wt;
+    const double* s3;
+    const InstDesc* insts;
+    const SquareItem* items;
+    const int* dlist;         // chunk's coherent-sum squares (item indices)
+    const void* ybuf;
+    double* partE;            // [n_delta][3][4]
+    int N;
+    double h;
+};
+
+struct AssembleArgs {
+    const InstDesc* insts;
+    const SquareItem* items;
+    const double* partD;
+    const double* partE;
+    const double* power;      // [n_ch]
+    const double* phi;
+    const double* psi;
+    double* eta;              // [n_cut]
+    double* sigma2;           // [n_cut] or null
+    double* terms;            // [n_cut][5] or null
+    double* psd;              // [n_cut][n_f] or null
+    int n_groups;
+    int n_f;
+    double rs;
+    double h;
+    int n_cut;
+};
+
+// Kernel launchers (isrs_kernels.hip).
+hipError_t launch_region(const RegionArgs& a, int n_items, bool fp32, hipStream_t st);
+hipError_t launch_egn(const EgnArgs& a, int n_delta, bool fp32, hipStream_t st);
+hipError_t launch_assemble(const AssembleArgs& a, hipStream_t st);
+
+}  // namespace isrs

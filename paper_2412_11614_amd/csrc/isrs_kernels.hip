@@ -1,0 +1,540 @@
+// isrs_kernels.hip -- gfx950 kernels of the ISRS-aware EGN hot path.
+//
+//   region   : per channel-pair square, the link function Upsilon (Eq. 22) on
+//              the N x N grid, with the per-span FWM efficiency factor from
+//              the segment closed form (Eqs. 7-10) or the Maclaurin form
+//              (Eqs. 2-6), and the GN island sums D (Eq. 17).
+//   egn      : coherent row / column / anti-diagonal / full sums of Upsilon
+//              for the modulation-format terms E, F, G, H (Eqs. 18-21).
+//   assemble : per CUT, the ordered FP64 sum over islands of Eq. 15 and the
+//              NLI coefficient of Eq. 11.
+//
+// Segment form as evaluated here: with q = exp((i chi - alpha) Delta) every
+// term of Eq. 9 is I_k = q^k I_0, I_0 = (q - 1) / (i chi - alpha), so
+//   mu_s = I_0 * sum_k g_k q^k,   g_k = SRS_G(z_k, f3abs)  (Eq. 8, z_k of Eq. 10)
+// and the sum is a Horner recurrence, four FMA-class operations per segment.
+// g_k depends on the point only through f1 + f2 (its anti-diagonal), so a
+// tile stages g for its 63 anti-diagonals in LDS and every point reads its
+// row with 16-byte loads.  Phases are formed in FP64 in revolutions and
+// reduced to [-1/2, 1/2] before the sine / cosine.
+#include "isrs_internal.h"
+
+namespace isrs {
+
+namespace {
+
+template <typename R>
+struct Prec;
+template <>
+struct Prec<float> {
+    using V2 = float2;
+    using Seg = SegRow32;
+    static constexpr int KC = 128;  // segments staged per pass
+    static constexpr int KP = 132;  // LDS row stride (words): 16-byte rows, rows 4 banks apart
+};
+template <>
+struct Prec<double> {
+    using V2 = double2;
+    using Seg = SegRow64;
+    static constexpr int KC = 64;
+    static constexpr int KP = 66;
+};
+
+__device__ __forceinline__ void sincos_rev(float t, float* s, float* c)
+{
+    // hardware sine / cosine take revolutions; |t| <= 1/2 here
+    *s = __builtin_amdgcn_sinf(t);
+    *c = __builtin_amdgcn_cosf(t);
+}
+
+__device__ __forceinline__ void sincos_rev(double t, double* s, double* c)
+{
+    sincospi(2.0 * t, s, c);
+}
+
+__device__ __forceinline__ float exp_r(float x) { return expf(x); }
+__device__ __forceinline__ double exp_r(double x) { return exp(x); }
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Deterministic block sum (fixed shuffle tree, then waves in order).
+__device__ double block_sum(double v, double* sh)
+{
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    for (int q = 0; q < THREADS / 64; ++q) r += sh[q];
+    return r;
+}
+
+template <typename R>
+__device__ __forceinline__ void horner_step(R& ar, R& ai, R qr, R qi, R g)
+{
+    const R nr = fma(ar, qr, fma(-ai, qi, g));
+    const R ni = fma(ar, qi, ai * qr);
+    ar = nr;
+    ai = ni;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(THREADS) region_kernel(RegionArgs a)
+{
+    using P = Prec<R>;
+    using V2 = typename P::V2;
+    using Seg = typename P::Seg;
+    constexpr int KC = P::KC, KP = P::KP;
+    __shared__ __align__(16) R g_lds[NAD * KP];
+    __shared__ double red[THREADS / 64];
+
+    const int tid = threadIdx.x;
+    const int item = a.item0 + blockIdx.x / a.n_groups;
+    const int grp = blockIdx.x % a.n_groups;
+    const SquareItem it = a.items[item];
+    const InstDesc in = a.insts[it.inst];
+    const int N = a.N, AD = 2 * N - 1;
+    const double h = a.h, df = a.spacing;
+    const double half_grid = 0.5 * (a.n_ch - 1);
+    // absolute offsets of the square (THz): d1 = d1b + f1, d2 = d2b + f2,
+    // a + b = sb + f1 + f2, a + b - c = x3b + f1 + f2, c = cabs
+    const double d1b = (it.k1 - in.cut) * df - in.f;
+    const double d2b = (it.k2 - in.cut) * df - in.f;
+    const double sb = (it.k1 + it.k2 - 2.0 * half_grid) * df;
+    const double x3b = (it.k1 + it.k2 - in.cut - half_grid) * df - in.f;
+    const double cabs = (in.cut - half_grid) * df + in.f;
+    const double* wt = a.wt + (size_t)in.nf_idx * 3 * AD;
+    const double* s3 = a.s3 + (size_t)in.nf_idx * 3 * AD;
+    const int* livep = a.livep + (size_t)in.nf_idx * 3 * (AD + 1);
+    const Seg* seg = reinterpret_cast<const Seg*>(a.seg);
+    V2* ybuf = it.y_slot >= 0 ? reinterpret_cast<V2*>(a.ybuf) + (size_t)it.y_slot * N * N : nullptr;
+
+    const int li = tid & (TILE - 1), r0 = tid / TILE;
+    double dacc[3] = {0.0, 0.0, 0.0};
+
+    const int tj_end = min(a.nt, (grp + 1) * a.spb);
+    for (int tj = grp * a.spb; tj < tj_end; ++tj) {
+        for (int ti = 0; ti < a.nt; ++ti) {
+            const int i0 = ti * TILE, j0 = tj * TILE, mb = i0 + j0;
+            // a tile is skipped when none of its anti-diagonals is live
+            bool live = false;
+            const int hi = min(mb + NAD, AD);
+#pragma unroll
+            for (int l = 0; l < 3; ++l)
+                if ((it.lmask >> l) & 1) live |= livep[l * (AD + 1) + hi] - livep[l * (AD + 1) + mb] > 0;
+            const int ip = i0 + li;
+            if (!live) {
+                if (ybuf) {
+#pragma unroll
+                    for (int r = 0; r < PPT; ++r) {
+                        const int jr = j0 + r0 + 8 * r;
+                        if (ip < N && jr < N) ybuf[(size_t)jr * N + ip] = V2{R(0), R(0)};
+                    }
+                }
+                continue;
+            }
+
+            const double f1 = (ip + 0.5 - 0.5 * N) * h;
+            const double d1 = d1b + f1;
+            double d12[PPT], sab[PPT];
+            int mm[PPT];
+            bool ok[PPT];
+            R ur[PPT], ui[PPT];  // Upsilon of each point
+#pragma unroll
+            for (int r = 0; r < PPT; ++r) {
+                const int jr = j0 + r0 + 8 * r;
+                const double f2 = (jr + 0.5 - 0.5 * N) * h;
+                ok[r] = ip < N && jr < N;
+                d12[r] = d1 * (d2b + f2);
+                sab[r] = sb + f1 + f2;
+                mm[r] = li + r0 + 8 * r;
+                ur[r] = R(0);
+                ui[r] = R(0);
+            }
+
+            for (int s = 0; s < a.n_sp; ++s) {
+                const SpanConst sc = a.spans[s];
+                R qr[PPT], qi[PPT], i0r[PPT], i0i[PPT], rr[PPT], ri[PPT];
+#pragma unroll
+                for (int r = 0; r < PPT; ++r) {
+                    // accumulated phase Theta_s of Eq. 22 and gain product
+                    double tt = d12[r] * (sc.p2r + sc.p3r * sab[r]);
+                    tt -= rint(tt);
+                    R st, ct;
+                    sincos_rev(R(tt), &st, &ct);
+                    R gm = R(sc.gamma);
+                    if (a.gain_mode == 1) gm *= exp_r(R(sc.pi_a - sc.pi_s * sab[r] + sc.pi_c * cabs));
+                    rr[r] = gm * ct;
+                    ri[r] = gm * st;
+                    const double chi = d12[r] * (sc.c2x + sc.c3x * sab[r]);
+                    const R al = R(sc.alpha), ch = R(chi);
+                    if (a.mu_method == 0) {
+                        double tq = d12[r] * (sc.c2r + sc.c3r * sab[r]);
+                        tq -= rint(tq);
+                        R sq, cq;
+                        sincos_rev(R(tq), &sq, &cq);
+                        qr[r] = R(sc.em) * cq;
+                        qi[r] = R(sc.em) * sq;
+                        // I_0 = (q - 1) / (i chi - alpha)
+                        const R vr = qr[r] - R(1), vi = qi[r];
+                        const R inv = R(1) / (al * al + ch * ch);
+                        i0r[r] = (-al * vr + ch * vi) * inv;
+                        i0i[r] = (-ch * vr - al * vi) * inv;
+                    } else {
+                        // Maclaurin form, Eqs. 4-6
+                        double tl = d12[r] * (sc.c2L + sc.c3L * sab[r]);
+                        tl -= rint(tl);
+                        R sl, cl;
+                        sincos_rev(R(tl), &sl, &cl);
+                        const R inv1 = R(1) / (al * al + ch * ch);
+                        const R inv2 = R(1) / (R(4) * al * al + ch * ch);
+                        // eta = (e^{(i chi - a) L} - 1) / (i chi - a)
+                        R vr = R(sc.emL) * cl - R(1), vi = R(sc.emL) * sl;
+                        const R er = (-al * vr + ch * vi) * inv1, ei = (-ch * vr - al * vi) * inv1;
+                        // (e^{(i chi - 2a) L} - 1) / (i chi - 2a)
+                        vr = R(sc.em2L) * cl - R(1);
+                        vi = R(sc.em2L) * sl;
+                        const R fr = (R(-2) * al * vr + ch * vi) * inv2, fi = (-ch * vr - R(2) * al * vi) * inv2;
+                        const R x3 = R(sab[r] - cabs);
+                        const R c = R(sc.pcr) * x3 / al;
+                        const R mr = er - c * (er - fr), mi = ei - c * (ei - fi);
+                        ur[r] += rr[r] * mr - ri[r] * mi;
+                        ui[r] += rr[r] * mi + ri[r] * mr;
+                    }
+                }
+                if (a.mu_method != 0) continue;
+
+                R ar[PPT], ai[PPT];
+#pragma unroll
+                for (int r = 0; r < PPT; ++r) {
+                    ar[r] = R(0);
+                    ai[r] = R(0);
+                }
+                const int Kp4 = (sc.K + 3) & ~3;
+                for (int kc1 = Kp4; kc1 > 0; kc1 -= KC) {
+                    const int kc0 = kc1 > KC ? kc1 - KC : 0;
+                    const int len = kc1 - kc0;
+                    __syncthreads();  // previous readers of g_lds are done
+                    // stage g_k(f3) = A_k exp(-zeta_k f3abs) for the tile's anti-diagonals:
+                    // one exp per run of STAGE_RUN anti-diagonals, then the step ratio
+                    const int runs = (NAD + STAGE_RUN - 1) / STAGE_RUN;
+                    for (int t = tid; t < len * runs; t += THREADS) {
+                        const int kk = t % len, run = t / len, k = kc0 + kk;
+                        R gA = R(0), z = R(0), rt = R(0);
+                        if (k < sc.K) {
+                            const Seg row = seg[sc.off + k];
+                            gA = row.A;
+                            z = row.zeta;
+                            rt = row.ratio;
+                        }
+                        const double x = x3b + (mb + run * STAGE_RUN + 1 - N) * h;
+                        R g = (k < sc.K) ? gA * exp_r(-z * R(x)) : R(0);
+#pragma unroll
+                        for (int q = 0; q < STAGE_RUN; ++q) {
+                            const int m = run * STAGE_RUN + q;
+                            if (m < NAD) g_lds[m * KP + kk] = g;
+                            g *= rt;
+                        }
+                    }
+                    __syncthreads();
+                    if constexpr (sizeof(R) == 4) {
+                        for (int kq = len - 4; kq >= 0; kq -= 4) {
+                            float4 v[PPT];
+#pragma unroll
+                            for (int r = 0; r < PPT; ++r)
+                                v[r] = *reinterpret_cast<const float4*>(&g_lds[mm[r] * KP + kq]);
+#pragma unroll
+                            for (int r = 0; r < PPT; ++r) {
+                                horner_step<R>(ar[r], ai[r], qr[r], qi[r], v[r].w);
+                                horner_step<R>(ar[r], ai[r], qr[r], qi[r], v[r].z);
+                                horner_step<R>(ar[r], ai[r], qr[r], qi[r], v[r].y);
+                                horner_step<R>(ar[r], ai[r], qr[r], qi[r], v[r].x);
+                            }
+                        }
+                    } else {
+                        for (int kq = len - 2; kq >= 0; kq -= 2) {
+                            double2 v[PPT];
+#pragma unroll
+                            for (int r = 0; r < PPT; ++r)
+                                v[r] = *reinterpret_cast<const double2*>(&g_lds[mm[r] * KP + kq]);
+#pragma unroll
+                            for (int r = 0; r < PPT; ++r) {
+                                horner_step<R>(ar[r], ai[r], qr[r], qi[r], v[r].y);
+                                horner_step<R>(ar[r], ai[r], qr[r], qi[r], v[r].x);
+                            }
+                        }
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < PPT; ++r) {
+                    // mu = I_0 * acc, Upsilon += gamma Pi e^{i Theta} mu
+                    const R mr = i0r[r] * ar[r] - i0i[r] * ai[r];
+                    const R mi = i0r[r] * ai[r] + i0i[r] * ar[r];
+                    ur[r] += rr[r] * mr - ri[r] * mi;
+                    ui[r] += rr[r] * mi + ri[r] * mr;
+                }
+            }
+
+            // GN island sums (Eq. 17) and the coherent-sum buffer
+            const double S1 = ip < N ? a.Sg[ip] : 0.0;
+#pragma unroll
+            for (int r = 0; r < PPT; ++r) {
+                if (!ok[r]) continue;
+                const int jr = j0 + r0 + 8 * r;
+                const int m = mb + mm[r];
+                const double S2 = a.Sg[jr];
+                const double u2 = (double)ur[r] * (double)ur[r] + (double)ui[r] * (double)ui[r];
+                const double v = S1 * S1 * S2 * S2 * u2;
+#pragma unroll
+                for (int l = 0; l < 3; ++l)
+                    if ((it.lmask >> l) & 1) {
+                        const double w3 = s3[l * AD + m];
+                        dacc[l] += wt[l * AD + m] * w3 * w3 * v;
+                    }
+                if (ybuf) ybuf[(size_t)jr * N + ip] = V2{ur[r], ui[r]};
+            }
+        }
+    }
+    double* out = a.partD + ((size_t)item * a.n_groups + grp) * 3;
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        const double v = block_sum(dacc[l], red);
+        if (tid == 0) out[l] = v;
+    }
+}
+
+// Coherent sums of one square for the format terms (bare, grid weights included):
+//   E_l = h^3 sum_j S2^2 |sum_i w S1 S3 U|^2      (rows,  Eq. 18)
+//   F_l = h^3 sum_i S1^2 |sum_j w S2 S3 U|^2      (columns, Eq. 19)
+//   G_l = h^3 sum_m w S3^2 |sum_{i+j=m} S1 S2 U|^2 (anti-diagonals, Eq. 20)
+//   H_l = h^4 |sum_ij w S1 S2 S3 U|^2            (Eq. 21)
+template <typename R>
+__global__ void __launch_bounds__(THREADS) egn_kernel(EgnArgs a)
+{
+    using V2 = typename Prec<R>::V2;
+    __shared__ double red[THREADS / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int item = a.dlist[blockIdx.x];
+    const SquareItem it = a.items[item];
+    const InstDesc in = a.insts[it.inst];
+    const int N = a.N, AD = 2 * N - 1;
+    const double h = a.h;
+    const double* wt = a.wt + (size_t)in.nf_idx * 3 * AD;
+    const double* s3 = a.s3 + (size_t)in.nf_idx * 3 * AD;
+    const V2* Y = reinterpret_cast<const V2*>(a.ybuf) + (size_t)it.y_slot * N * N;
+    const double* Sg = a.Sg;
+    const int em = it.egn_mask;
+    double res[3][4];
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) res[l][t] = 0.0;
+
+    // E: rows, one wave per row
+    if (em & 0x111) {
+        double e[3] = {0.0, 0.0, 0.0};
+        for (int j = wave; j < N; j += THREADS / 64) {
+            double cr[3] = {0, 0, 0}, ci[3] = {0, 0, 0};
+            for (int i = lane; i < N; i += 64) {
+                const V2 y = Y[(size_t)j * N + i];
+                const int m = i + j;
+#pragma unroll
+                for (int l = 0; l < 3; ++l) {
+                    const double w = wt[l * AD + m] * s3[l * AD + m] * Sg[i];
+                    cr[l] += w * (double)y.x;
+                    ci[l] += w * (double)y.y;
+                }
+            }
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+                const double xr = wave_sum(cr[l]), xi = wave_sum(ci[l]);
+                e[l] += Sg[j] * Sg[j] * (xr * xr + xi * xi);
+            }
+        }
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            // each wave holds its rows' total in every lane; add waves in order
+            __syncthreads();
+            if (lane == 0) red[wave] = e[l];
+            __syncthreads();
+            double s = 0.0;
+            for (int q = 0; q < THREADS / 64; ++q) s += red[q];
+            res[l][0] = h * h * h * s;
+        }
+    }
+    // F: columns, one thread per column
+    if (em & 0x222) {
+        double f[3] = {0.0, 0.0, 0.0};
+        for (int i = tid; i < N; i += THREADS) {
+            double cr[3] = {0, 0, 0}, ci[3] = {0, 0, 0};
+            for (int j = 0; j < N; ++j) {
+                const V2 y = Y[(size_t)j * N + i];
+                const int m = i + j;
+#pragma unroll
+                for (int l = 0; l < 3; ++l) {
+                    const double w = wt[l * AD + m] * s3[l * AD + m] * Sg[j];
+                    cr[l] += w * (double)y.x;
+                    ci[l] += w * (double)y.y;
+                }
+            }
+#pragma unroll
+            for (int l = 0; l < 3; ++l) f[l] += Sg[i] * Sg[i] * (cr[l] * cr[l] + ci[l] * ci[l]);
+        }
+#pragma unroll
+        for (int l = 0; l < 3; ++l) res[l][1] = h * h * h * block_sum(f[l], red);
+    }
+    // G: anti-diagonals, one thread per anti-diagonal
+    if (em & 0x444) {
+        double g[3] = {0.0, 0.0, 0.0};
+        for (int m = tid; m < AD; m += THREADS) {
+            double cr = 0.0, ci = 0.0;
+            const int i0 = m - (N - 1) > 0 ? m - (N - 1) : 0, i1 = m < N - 1 ? m : N - 1;
+            for (int i = i0; i <= i1; ++i) {
+                const V2 y = Y[(size_t)(m - i) * N + i];
+                const double w = Sg[i] * Sg[m - i];
+                cr += w * (double)y.x;
+                ci += w * (double)y.y;
+            }
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+                const double w3 = s3[l * AD + m];
+                g[l] += wt[l * AD + m] * w3 * w3 * (cr * cr + ci * ci);
+            }
+        }
+#pragma unroll
+        for (int l = 0; l < 3; ++l) res[l][2] = h * h * h * block_sum(g[l], red);
+    }
+    // H: full sum
+    if (em & 0x888) {
+        double cr[3] = {0, 0, 0}, ci[3] = {0, 0, 0};
+        for (int p = tid; p < N * N; p += THREADS) {
+            const int i = p % N, j = p / N, m = i + j;
+            const V2 y = Y[p];
+            const double s12 = Sg[i] * Sg[j];
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+                const double w = wt[l * AD + m] * s3[l * AD + m] * s12;
+                cr[l] += w * (double)y.x;
+                ci[l] += w * (double)y.y;
+            }
+        }
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            const double xr = block_sum(cr[l], red), xi = block_sum(ci[l], red);
+            res[l][3] = h * h * h * h * (xr * xr + xi * xi);
+        }
+    }
+    if (tid == 0) {
+        double* o = a.partE + (size_t)it.d_index * 12;
+#pragma unroll
+        for (int l = 0; l < 3; ++l)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) o[l * 4 + t] = ((em >> (4 * l + t)) & 1) ? res[l][t] : 0.0;
+    }
+}
+
+// Per CUT: sigma^2 = sum_f w_f sum_islands P1 P2 P3 [c_D R^3 D + Phi c_E R^2 E + ...],
+// summed in a fixed order (Eq. 15), eta = sigma^2 / P^3 (Eq. 11).
+__global__ void __launch_bounds__(THREADS) assemble_kernel(AssembleArgs a)
+{
+    __shared__ double red[THREADS / 64];
+    const int q = blockIdx.x, tid = threadIdx.x;
+    const double R = a.rs, R2 = R * R, R3 = R2 * R;
+    const double cD = 16.0 / 27.0, cE = 16.0 / 27.0, cF = 32.0 / 81.0, cG = 16.0 / 81.0, cH = 16.0 / 81.0;
+    const double h2 = a.h * a.h;
+    double s2 = 0.0, tot[5] = {0, 0, 0, 0, 0};
+    int cut = 0;
+    for (int n = 0; n < a.n_f; ++n) {
+        const InstDesc in = a.insts[q * a.n_f + n];
+        cut = in.cut;
+        double t[5] = {0, 0, 0, 0, 0};
+        for (int sq = in.sq_begin + tid; sq < in.sq_end; sq += THREADS) {
+            const SquareItem it = a.items[sq];
+            const double* pd = a.partD + (size_t)sq * a.n_groups * 3;
+            const double* pe = it.d_index >= 0 ? a.partE + (size_t)it.d_index * 12 : nullptr;
+            const bool folded = it.k1 != it.k2;
+            for (int l = 0; l < 3; ++l) {
+                if (!((it.lmask >> l) & 1)) continue;
+                const int k3 = it.k1 + it.k2 - in.cut + (l - 1);
+                const double P = a.power[it.k1] * a.power[it.k2] * a.power[k3];
+                double D = 0.0;
+                for (int g = 0; g < a.n_groups; ++g) D += pd[g * 3 + l];
+                t[0] += P * it.mult * cD * R3 * h2 * D;
+                if (!pe) continue;
+                const double* e = pe + l * 4;
+                if (folded) {
+                    // the mirror square (k2, k1) has F = this square's E when k3 == k1
+                    // and E = this square's F when k3 == k2 (f1 <-> f2 symmetry)
+                    if (k3 == it.k1) {
+                        t[1] += P * a.phi[it.k1] * cE * R2 * e[0];
+                        t[2] += P * a.phi[it.k1] * cF * R2 * e[0];
+                    }
+                    if (k3 == it.k2) {
+                        t[2] += P * a.phi[it.k2] * cF * R2 * e[1];
+                        t[1] += P * a.phi[it.k2] * cE * R2 * e[1];
+                    }
+                } else {
+                    if (k3 == it.k1) t[1] += P * a.phi[it.k1] * cE * R2 * e[0];
+                    if (k3 == it.k2) t[2] += P * a.phi[it.k2] * cF * R2 * e[1];
+                    t[3] += P * a.phi[it.k1] * cG * R2 * e[2];
+                    if (k3 == it.k2) t[4] += P * a.psi[it.k1] * cH * R * e[3];
+                }
+            }
+        }
+        double G = 0.0;
+        double tb[5];
+        for (int u = 0; u < 5; ++u) {
+            tb[u] = block_sum(t[u], red);
+            G += tb[u];
+        }
+        const double wf = a.n_f == 1 ? R : R / a.n_f;
+        if (tid == 0 && a.psd) a.psd[(size_t)q * a.n_f + n] = G;
+        s2 += wf * G;
+        for (int u = 0; u < 5; ++u) tot[u] += wf * tb[u];
+    }
+    if (tid == 0) {
+        const double P = a.power[cut];
+        a.eta[q] = s2 / (P * P * P);
+        if (a.sigma2) a.sigma2[q] = s2;
+        if (a.terms)
+            for (int u = 0; u < 5; ++u) a.terms[(size_t)q * 5 + u] = tot[u];
+    }
+}
+
+}  // namespace
+
+hipError_t launch_region(const RegionArgs& a, int n_items, bool fp32, hipStream_t st)
+{
+    const unsigned grid = (unsigned)n_items * (unsigned)a.n_groups;
+    if (grid == 0) return hipSuccess;
+    if (fp32)
+        hipLaunchKernelGGL(region_kernel<float>, dim3(grid), dim3(THREADS), 0, st, a);
+    else
+        hipLaunchKernelGGL(region_kernel<double>, dim3(grid), dim3(THREADS), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_egn(const EgnArgs& a, int n_delta, bool fp32, hipStream_t st)
+{
+    if (n_delta == 0) return hipSuccess;
+    if (fp32)
+        hipLaunchKernelGGL(egn_kernel<float>, dim3(n_delta), dim3(THREADS), 0, st, a);
+    else
+        hipLaunchKernelGGL(egn_kernel<double>, dim3(n_delta), dim3(THREADS), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_assemble(const AssembleArgs& a, hipStream_t st)
+{
+    if (a.n_cut == 0) return hipSuccess;
+    hipLaunchKernelGGL(assemble_kernel, dim3(a.n_cut), dim3(THREADS), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace isrs

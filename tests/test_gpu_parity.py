@@ -1,0 +1,183 @@
+"""GPU parity: the HIP path through the C-ABI against the CPU oracle.
+
+Bars:
+  * FP64 path vs the oracle's segment form (same approximation of Eq. 23,
+    different code): |eta error| <= 1e-9 dB, island integrals to 1e-9 rel.
+  * every path vs the oracle's integral form (the reference method):
+    |eta error| <= 0.01 dB.
+  * FP32-integrand / FP64-phase path vs the oracle: <= 0.01 dB.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2412_11614_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FP64 = W.PREC_FP64
+FP32 = W.PREC_FP32_PHASE64
+
+
+def db(x, ref):
+    return 10.0 * np.log10(np.asarray(x) / np.asarray(ref))
+
+
+@pytest.fixture(scope="module")
+def engine():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2412_11614_amd import _lib
+    e = _lib.Engine(0)
+    yield e
+    e.close()
+
+
+def _run(engine, wl, **kw):
+    engine.load(wl)
+    return engine.eval_eta(wl.numerics, wl.cuts, **kw)
+
+
+def test_single_span_11ch_fp64(engine):
+    """11 x 64 GBd, one 80 km span, GN only, centre CUT, 64 x 64 grid."""
+    wl = W.single_span_11ch()
+    got = _run(engine, wl, precision=FP64)
+    seg = oracle.eval_cuts(wl, method="segment")
+    ref = oracle.eval_cuts(wl, method="integral")
+    print("eta", got["eta"], "seg", seg["eta"], "int", ref["eta"], flush=True)
+    assert np.max(np.abs(db(got["eta"], seg["eta"]))) <= 1e-9
+    assert np.max(np.abs(db(got["eta"], ref["eta"]))) <= 1e-2
+    assert np.allclose(got["terms"], seg["terms"], rtol=1e-10, atol=0)
+    # all CUTs of the grid
+    allc = np.arange(11, dtype=np.int32)
+    got = engine.eval_eta(wl.numerics, allc, precision=FP64)
+    seg = oracle.eval_cuts(wl, cuts=allc, method="segment")
+    assert np.max(np.abs(db(got["eta"], seg["eta"]))) <= 1e-9
+
+
+@pytest.mark.parametrize("n_grid", [40, 33, 8])
+def test_mixed_egn_fp64_matches_segment_oracle(engine, n_grid):
+    """Mixed formats, uneven spans, an inactive slot, EGN terms; grids with a
+    ragged last tile (40, 33) and a single partial tile (8)."""
+    wl = W.small_mixed(n_ch=7, n_spans=3, n_grid=n_grid)
+    got = _run(engine, wl, precision=FP64)
+    seg = oracle.eval_cuts(wl, method="segment")
+    err = db(got["eta"], seg["eta"])
+    print("n", n_grid, "max err dB", np.max(np.abs(err)), flush=True)
+    assert np.max(np.abs(err)) <= 1e-9
+    assert np.allclose(got["terms"], seg["terms"], rtol=1e-9, atol=1e-12 * np.abs(seg["sigma2"]).max())
+
+
+def test_mixed_egn_against_integral_form(engine):
+    wl = W.small_mixed(n_ch=7, n_spans=3, n_grid=40)
+    ref = oracle.eval_cuts(wl, method="integral")
+    for prec in (FP64, FP32):
+        got = _run(engine, wl, precision=prec)
+        err = db(got["eta"], ref["eta"])
+        print("prec", prec, "max err dB vs integral", np.max(np.abs(err)), flush=True)
+        assert np.max(np.abs(err)) <= 1e-2
+
+
+def test_fp32_phase64_close_to_fp64(engine):
+    wl = W.small_mixed(n_ch=7, n_spans=3, n_grid=40)
+    a = _run(engine, wl, precision=FP64)["eta"]
+    b = _run(engine, wl, precision=FP32)["eta"]
+    err = db(b, a)
+    print("fp32 vs fp64 dB", err, flush=True)
+    assert np.max(np.abs(err)) <= 2e-3
+
+
+def test_island_partials_fp64(engine):
+    wl = W.small_mixed(n_ch=7, n_spans=3, n_grid=36)
+    engine.load(wl)
+    cut = 3
+    squares = [(3, 3), (2, 4), (4, 2), (0, 6), (6, 0), (1, 3), (3, 1), (2, 2), (4, 3), (0, 0), (5, 6)]
+    got = engine.eval_islands(wl.numerics, cut, squares, precision=FP64)
+    for (k1, k2), g in zip(squares, got):
+        ref = oracle.square_terms(wl, cut, k1, k2, method="segment")
+        scale = np.abs(ref).max() + 1e-300
+        assert np.allclose(g, ref, rtol=1e-9, atol=1e-12 * scale), ((k1, k2), g, ref)
+
+
+def test_loss_only_gain(engine):
+    wl = W.small_mixed(n_ch=6, n_spans=3, n_grid=24, gain_mode=W.GAIN_LOSS_ONLY)
+    got = _run(engine, wl, precision=FP64)
+    seg = oracle.eval_cuts(wl, method="segment")
+    assert np.max(np.abs(db(got["eta"], seg["eta"]))) <= 1e-9
+    got32 = _run(engine, wl, precision=FP32)
+    assert np.max(np.abs(db(got32["eta"], seg["eta"]))) <= 1e-2
+
+
+def test_maclaurin_form(engine):
+    wl = W.small_mixed(n_ch=6, n_spans=2, n_grid=24)
+    got = _run(engine, wl, precision=FP64, mu_method=W.MU_MACLAURIN)
+    mac = oracle.eval_cuts(wl, method="maclaurin")
+    assert np.max(np.abs(db(got["eta"], mac["eta"]))) <= 1e-9
+
+
+def test_outer_frequency_samples_and_psd(engine):
+    wl = W.small_mixed(n_ch=5, n_spans=2, n_grid=20).with_numerics(n_f=3)
+    engine.load(wl)
+    got = engine.eval_eta(wl.numerics, wl.cuts, precision=FP64)
+    seg = oracle.eval_cuts(wl, method="segment")
+    assert np.max(np.abs(db(got["eta"], seg["eta"]))) <= 1e-9
+    f, psd = engine.eval_psd(wl.numerics, wl.cuts, precision=FP64)
+    assert np.allclose(psd, seg["psd"], rtol=1e-9)
+    rs = wl.spectrum.symbol_rate_thz
+    assert np.allclose(f[0], [-rs / 3, 0.0, rs / 3])
+    assert np.allclose((rs / 3) * psd.sum(axis=1), got["sigma2"], rtol=1e-12)
+
+
+def test_rolloff_zero_boundary_ties(engine):
+    """Rs = spacing, roll-off 0: island boundaries fall on grid points (the
+    half-weight rule), as in the S+C+L workload."""
+    wl = W.sclband_150ch_40span(n_grid=16)
+    sp = W.spectrum_from(9, 0.1, 0.1, 0.0, wl.spectrum.power_w[:9] * 150 / 9, wl.spectrum.formats[:9])
+    w2 = W.Workload("ties", sp, W.Link(wl.link.spans[:3]), W.Numerics(n_grid=16, egn=1), np.arange(9, dtype=np.int32))
+    got = _run(engine, w2, precision=FP64)
+    seg = oracle.eval_cuts(w2, method="segment")
+    assert np.max(np.abs(db(got["eta"], seg["eta"]))) <= 1e-9
+    got32 = _run(engine, w2, precision=FP32)
+    ref = oracle.eval_cuts(w2, method="integral")
+    assert np.max(np.abs(db(got32["eta"], ref["eta"]))) <= 1e-2
+
+
+def test_long_span_segment_chunking(engine):
+    """K = 160 segments: more than one staged chunk per span in both precisions."""
+    wl = W.small_mixed(n_ch=5, n_spans=2, n_grid=16)
+    wl.numerics.dz_km = 0.5
+    got = _run(engine, wl, precision=FP64)
+    seg = oracle.eval_cuts(wl, method="segment")
+    assert np.max(np.abs(db(got["eta"], seg["eta"]))) <= 1e-9
+    got32 = _run(engine, wl, precision=FP32)
+    assert np.max(np.abs(db(got32["eta"], seg["eta"]))) <= 1e-2
+
+
+def test_single_channel_and_one_segment(engine):
+    sp = W.spectrum_from(1, 0.05, 0.032, 0.2, [1e-3], ["16qam"])
+    wl = W.Workload("one", sp, W.Link(W.make_spans([40.0])), W.Numerics(n_grid=8, dz_km=100.0, egn=1),
+                    np.array([0], dtype=np.int32))
+    got = _run(engine, wl, precision=FP64)
+    seg = oracle.eval_cuts(wl, method="segment")
+    assert np.max(np.abs(db(got["eta"], seg["eta"]))) <= 1e-9
+
+
+def test_deterministic(engine):
+    wl = W.small_mixed(n_ch=7, n_spans=3, n_grid=40)
+    for prec in (FP64, FP32):
+        a = _run(engine, wl, precision=prec)
+        b = _run(engine, wl, precision=prec)
+        assert np.array_equal(a["eta"], b["eta"]) and np.array_equal(a["terms"], b["terms"])
+
+
+def test_errors_leave_context_usable(engine):
+    from paper_2412_11614_amd import _lib
+    wl = W.small_mixed(n_ch=5, n_spans=2, n_grid=8)
+    engine.load(wl)
+    with pytest.raises(_lib.IsrsError) as ei:
+        engine.eval_eta(wl.numerics, [7])
+    assert ei.value.code == _lib.ISRS_E_ARG
+    with pytest.raises(_lib.IsrsError):
+        engine.eval_eta(wl.numerics, [0], n=0)
+    got = engine.eval_eta(wl.numerics, wl.cuts, precision=FP64)
+    assert np.all(np.isfinite(got["eta"]))
