@@ -1,0 +1,187 @@
+"""Throughput of the ISRS-EGN hot path on one MI355X.
+
+One step = one pass of the whole hot path (segment tables, island work list,
+region kernel over every folded channel-pair square, coherent EGN sums,
+per-CUT assembly) for every CUT of the C+L workload: 100 x 96 GBd channels on
+a 100 GHz grid (10 THz), 10 spans of 80-100 km, 256 x 256 grid per square,
+FP32 integrand with FP64 phases and sums.  Inputs are resident on the GPU
+when the timed region starts; outputs stay on the GPU.
+
+Prints one JSON line.  The CPU-baseline leg times the FP64 oracle (integral
+form of the z-integral) on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+# Peak of the ALU-bound region kernel: FP32 FMA without packed instructions
+# (packed FP32 is disabled at build time): 256 CU x 4 SIMD x 16 lanes x
+# 2 FLOP x 2.4 GHz.  The same figure is the FP64 vector peak.
+PEAK_ALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+PEAK_PACKED_FP32_TFLOPS = 157.3
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(wl, n_squares, seed=0):
+    """Times the oracle (integral-form FWM factor, FP64) on n_squares randomly
+    drawn live channel-pair squares of the middle CUT at the full grid, using
+    all host cores (one square per thread), and scales to CUTs per second."""
+    import concurrent.futures as cf
+
+    import oracle
+
+    oracle.lib()
+    sp = wl.spectrum
+    nc = sp.n_ch
+    cut = nc // 2
+    act = sp.power_w > 0
+    live = []
+    for k1 in range(nc):
+        for k2 in range(nc):
+            if not (act[k1] and act[k2]):
+                continue
+            if any(0 <= k1 + k2 - cut + l < nc and act[k1 + k2 - cut + l] for l in (-1, 0, 1)):
+                live.append((k1, k2))
+    rng = np.random.default_rng(seed)
+    pick = [live[i] for i in rng.choice(len(live), size=n_squares, replace=False)]
+    cores = os.cpu_count() or 1
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        pass
+    threads = max(1, min(cores, n_squares))
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(threads) as ex:
+        list(ex.map(lambda kk: oracle.square_terms(wl, cut, kk[0], kk[1], method="integral"), pick))
+    wall = time.perf_counter() - t0
+    cut_seconds = wall / n_squares * len(live)
+    return {"value": 1.0 / cut_seconds, "unit": "CUT/s", "cores": threads, "kind": "oracle",
+            "sample": (f"{n_squares} random live squares of CUT {cut} (of {len(live)}) at the full "
+                       f"{wl.numerics.n_grid}x{wl.numerics.n_grid} grid, 10 spans, integral-form mu; "
+                       f"{wall:.1f} s wall on {threads} threads, scaled by squares per CUT")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--grid", type=int, default=256)
+    ap.add_argument("--cpu-squares", type=int, default=48)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the path is single-GPU "
+              "and shards by (CUT, square) lists without collectives in the compute.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2412_11614_amd import _lib, workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    wl = W.cl_100ch_10span(n_grid=args.grid, precision=W.PREC_FP32_PHASE64)
+    cuts = wl.cuts
+    n_cut = len(cuts)
+    stream = torch.cuda.current_stream()
+    eng = _lib.Engine(0, stream=stream.cuda_stream)
+    eng.load(wl)
+    eta = torch.empty(n_cut, dtype=torch.float64, device=dev)
+    s2 = torch.empty(n_cut, dtype=torch.float64, device=dev)
+    terms = torch.empty(n_cut * 5, dtype=torch.float64, device=dev)
+
+    def step(prec):
+        eng.eval_eta_dev(wl.numerics, cuts, eta, s2, terms, precision=prec)
+
+    log(f"warmup {args.warmup} step(s), {n_cut} CUTs, grid {args.grid}")
+    for _ in range(args.warmup):
+        step(W.PREC_FP32_PHASE64)
+    torch.cuda.synchronize()
+    log("timed steps")
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(W.PREC_FP32_PHASE64)
+        log(f"step {i} queued")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    eta32 = eta.cpu().numpy().copy()
+    value = n_cut * args.steps / elapsed
+
+    # kernel timing with HIP events on the library's stream (one extra step)
+    eng.set_profiling(True)
+    step(W.PREC_FP32_PHASE64)
+    torch.cuda.synchronize()
+    st = eng.stats()
+    eng.set_profiling(False)
+    per_launch_ms = st.region_ms / max(1, st.region_launches)
+    achieved = st.alg_flop / st.region_launches / (per_launch_ms * 1e-3) / 1e12
+    log(f"region kernel {st.region_ms:.1f} ms over {st.region_launches} launch(es); egn {st.egn_ms:.1f} ms; "
+        f"host prep {st.host_prep_ms:.1f} ms; {achieved:.2f} TFLOP/s")
+
+    out = {
+        "metric": "CUT NLI coeffs/sec at <=0.01 dB vs FP64 oracle",
+        "value": value,
+        "unit": "CUT/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": (f"C+L 10 THz: 100 x 96 GBd on 100 GHz, roll-off 0.04, 20 dBm with +-2 dB tilt, "
+                                f"10 spans U[80,100] km (seed 2), 16QAM/64QAM alternating, EGN on, "
+                                f"{args.grid}x{args.grid} points per square, all {n_cut} CUTs, dz 1 km, "
+                                f"FP32 integrand / FP64 phase and sums"),
+                   "n_cut": int(n_cut), "grid": args.grid, "spans": 10, "channels": 100},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_ALU_TFLOPS, "traffic": None,
+                     "kernel": "region_kernel<float>", "per_launch_ms": per_launch_ms,
+                     "alg_flop_per_launch": st.alg_flop / st.region_launches,
+                     "peak_packed_fp32": PEAK_PACKED_FP32_TFLOPS},
+        "detail": {"region_ms": st.region_ms, "egn_ms": st.egn_ms, "assemble_ms": st.assemble_ms,
+                   "host_prep_ms": st.host_prep_ms, "squares": st.n_squares,
+                   "delta_squares": st.n_delta_squares, "live_points": st.n_points_live,
+                   "horner_steps": st.horner_steps},
+    }
+
+    if not args.no_fp64:
+        # accuracy gate on the full workload: FP32 path vs the FP64 path (the
+        # FP64 path is parity-tested against the oracle); plus its throughput
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        step(W.PREC_FP64)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t1
+        eta64 = eta.cpu().numpy()
+        err = np.abs(10 * np.log10(eta32 / eta64))
+        out["accuracy"] = {"fp32_vs_fp64_max_abs_db": float(err.max()), "fp32_vs_fp64_mean_abs_db": float(err.mean()),
+                           "within_0p01_db": bool(err.max() <= 0.01)}
+        out["fp64_value"] = n_cut / t64
+    eng.close()
+
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_squares)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
