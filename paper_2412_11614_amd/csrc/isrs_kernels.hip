@@ -11,12 +11,16 @@
 //
 // Segment form as evaluated here: with q = exp((i chi - alpha) Delta) every
 // term of Eq. 9 is I_k = q^k I_0, I_0 = (q - 1) / (i chi - alpha), so
-//   mu_s = I_0 * sum_k g_k q^k,   g_k = SRS_G(z_k, f3abs)  (Eq. 8, z_k of Eq. 10)
-// and the sum is a Horner recurrence, four FMA-class operations per segment.
-// g_k depends on the point only through f1 + f2 (its anti-diagonal), so a
-// tile stages g for its 63 anti-diagonals in LDS and every point reads its
-// row with 16-byte loads.  Phases are formed in FP64 in revolutions and
-// reduced to [-1/2, 1/2] before the sine / cosine.
+//   mu_s = I_0 * P(q),   P(q) = sum_k g_k q^k,   g_k = SRS_G(z_k, f3abs)
+// (Eq. 8, z_k of Eq. 10).  P has real coefficients, so it is evaluated with
+// the Goertzel recurrence (G. Goertzel, 1958): with t = 2 Re q and s = |q|^2,
+//   b_k = g_k + t b_{k+1} - s b_{k+2},   P(q) = b_0 - conj(q) b_1,
+// two real FMAs per segment (q and conj(q) are the roots of x^2 - t x + s).
+// s = exp(-2 alpha Delta) is a per-span constant.  g_k depends on the point
+// only through f1 + f2 (its anti-diagonal), so a tile stages g for its 63
+// anti-diagonals in LDS; each wave covers 8 x 8 point blocks, so the 64 lanes
+// of a read touch 15 rows and share them.  Phases are formed in FP64 in
+// revolutions and reduced to [-1/2, 1/2] before the sine / cosine.
 #include "isrs_internal.h"
 
 namespace isrs {
@@ -28,16 +32,20 @@ struct Prec;
 template <>
 struct Prec<float> {
     using V2 = float2;
+    using Vec = float4;             // one 16-byte LDS read = 4 segments
     using Seg = SegRow32;
     static constexpr int KC = 128;  // segments staged per pass
-    static constexpr int KP = 132;  // LDS row stride (words): 16-byte rows, rows 4 banks apart
+    static constexpr int KP = 132;  // LDS row stride (elements): 16-byte rows, 4 banks apart
+    static constexpr int VW = 4;    // elements per Vec
 };
 template <>
 struct Prec<double> {
     using V2 = double2;
+    using Vec = double2;
     using Seg = SegRow64;
     static constexpr int KC = 64;
     static constexpr int KP = 66;
+    static constexpr int VW = 2;
 };
 
 __device__ __forceinline__ void sincos_rev(float t, float* s, float* c)
@@ -75,24 +83,27 @@ __device__ double block_sum(double v, double* sh)
     return r;
 }
 
+// b_k = g_k + t b_{k+1} - s b_{k+2}  (ms = -s)
 template <typename R>
-__device__ __forceinline__ void horner_step(R& ar, R& ai, R qr, R qi, R g)
+__device__ __forceinline__ void goertzel_step(R& b1, R& b2, R t, R ms, R g)
 {
-    const R nr = fma(ar, qr, fma(-ai, qi, g));
-    const R ni = fma(ar, qi, ai * qr);
-    ar = nr;
-    ai = ni;
+    const R b0 = fma(ms, b2, fma(t, b1, g));
+    b2 = b1;
+    b1 = b0;
 }
 
-template <typename R>
+template <typename R, int MU>
 __global__ void __launch_bounds__(THREADS) region_kernel(RegionArgs a)
 {
     using P = Prec<R>;
     using V2 = typename P::V2;
+    using Vec = typename P::Vec;
     using Seg = typename P::Seg;
-    constexpr int KC = P::KC, KP = P::KP;
-    __shared__ __align__(16) R g_lds[NAD * KP];
+    constexpr int KC = P::KC, KP = P::KP, VW = P::VW, KPV = KP / VW;
+    // g rows of the tile's anti-diagonals; read as 16-byte vectors, written as scalars
+    __shared__ Vec g_vec[NAD * KPV];
     __shared__ double red[THREADS / 64];
+    R* const g_lds = reinterpret_cast<R*>(g_vec);
 
     const int tid = threadIdx.x;
     const int item = a.item0 + blockIdx.x / a.n_groups;
@@ -115,7 +126,9 @@ __global__ void __launch_bounds__(THREADS) region_kernel(RegionArgs a)
     const Seg* seg = reinterpret_cast<const Seg*>(a.seg);
     V2* ybuf = it.y_slot >= 0 ? reinterpret_cast<V2*>(a.ybuf) + (size_t)it.y_slot * N * N : nullptr;
 
-    const int li = tid & (TILE - 1), r0 = tid / TILE;
+    // wave w owns tile columns 8w..8w+7; point r of a lane is in rows 8r..8r+7
+    const int lane = tid & 63, wv = tid >> 6;
+    const int li = 8 * wv + (lane & 7), lj = lane >> 3;
     double dacc[3] = {0.0, 0.0, 0.0};
 
     const int tj_end = min(a.nt, (grp + 1) * a.spb);
@@ -133,7 +146,7 @@ __global__ void __launch_bounds__(THREADS) region_kernel(RegionArgs a)
                 if (ybuf) {
 #pragma unroll
                     for (int r = 0; r < PPT; ++r) {
-                        const int jr = j0 + r0 + 8 * r;
+                        const int jr = j0 + lj + 8 * r;
                         if (ip < N && jr < N) ybuf[(size_t)jr * N + ip] = V2{R(0), R(0)};
                     }
                 }
@@ -148,12 +161,12 @@ __global__ void __launch_bounds__(THREADS) region_kernel(RegionArgs a)
             R ur[PPT], ui[PPT];  // Upsilon of each point
 #pragma unroll
             for (int r = 0; r < PPT; ++r) {
-                const int jr = j0 + r0 + 8 * r;
+                const int jr = j0 + lj + 8 * r;
                 const double f2 = (jr + 0.5 - 0.5 * N) * h;
                 ok[r] = ip < N && jr < N;
                 d12[r] = d1 * (d2b + f2);
                 sab[r] = sb + f1 + f2;
-                mm[r] = li + r0 + 8 * r;
+                mm[r] = li + lj + 8 * r;
                 ur[r] = R(0);
                 ui[r] = R(0);
             }
@@ -174,7 +187,7 @@ __global__ void __launch_bounds__(THREADS) region_kernel(RegionArgs a)
                     ri[r] = gm * st;
                     const double chi = d12[r] * (sc.c2x + sc.c3x * sab[r]);
                     const R al = R(sc.alpha), ch = R(chi);
-                    if (a.mu_method == 0) {
+                    if constexpr (MU == 0) {
                         double tq = d12[r] * (sc.c2r + sc.c3r * sab[r]);
                         tq -= rint(tq);
                         R sq, cq;
@@ -208,14 +221,17 @@ __global__ void __launch_bounds__(THREADS) region_kernel(RegionArgs a)
                         ui[r] += rr[r] * mi + ri[r] * mr;
                     }
                 }
-                if (a.mu_method != 0) continue;
+                if constexpr (MU != 0) continue;
 
-                R ar[PPT], ai[PPT];
+                // Goertzel state per point; s = |q|^2 is uniform over the span
+                R b1[PPT], b2[PPT], tq2[PPT];
 #pragma unroll
                 for (int r = 0; r < PPT; ++r) {
-                    ar[r] = R(0);
-                    ai[r] = R(0);
+                    b1[r] = R(0);
+                    b2[r] = R(0);
+                    tq2[r] = R(2) * qr[r];
                 }
+                const R ms = R(-(sc.em * sc.em));
                 const int Kp4 = (sc.K + 3) & ~3;
                 for (int kc1 = Kp4; kc1 > 0; kc1 -= KC) {
                     const int kc0 = kc1 > KC ? kc1 - KC : 0;
@@ -243,39 +259,30 @@ __global__ void __launch_bounds__(THREADS) region_kernel(RegionArgs a)
                         }
                     }
                     __syncthreads();
-                    if constexpr (sizeof(R) == 4) {
-                        for (int kq = len - 4; kq >= 0; kq -= 4) {
-                            float4 v[PPT];
+                    // every point reads its own anti-diagonal row: one base index
+                    // plus compile-time row offsets (8 rows apart per point)
+                    const Vec* gb = g_vec + (li + lj) * KPV;
+                    for (int kv = len / VW - 1; kv >= 0; --kv) {
+                        Vec v[PPT];
 #pragma unroll
-                            for (int r = 0; r < PPT; ++r)
-                                v[r] = *reinterpret_cast<const float4*>(&g_lds[mm[r] * KP + kq]);
+                        for (int r = 0; r < PPT; ++r) v[r] = gb[r * 8 * KPV + kv];
 #pragma unroll
-                            for (int r = 0; r < PPT; ++r) {
-                                horner_step<R>(ar[r], ai[r], qr[r], qi[r], v[r].w);
-                                horner_step<R>(ar[r], ai[r], qr[r], qi[r], v[r].z);
-                                horner_step<R>(ar[r], ai[r], qr[r], qi[r], v[r].y);
-                                horner_step<R>(ar[r], ai[r], qr[r], qi[r], v[r].x);
+                        for (int r = 0; r < PPT; ++r) {
+                            if constexpr (VW == 4) {
+                                goertzel_step<R>(b1[r], b2[r], tq2[r], ms, v[r].w);
+                                goertzel_step<R>(b1[r], b2[r], tq2[r], ms, v[r].z);
                             }
-                        }
-                    } else {
-                        for (int kq = len - 2; kq >= 0; kq -= 2) {
-                            double2 v[PPT];
-#pragma unroll
-                            for (int r = 0; r < PPT; ++r)
-                                v[r] = *reinterpret_cast<const double2*>(&g_lds[mm[r] * KP + kq]);
-#pragma unroll
-                            for (int r = 0; r < PPT; ++r) {
-                                horner_step<R>(ar[r], ai[r], qr[r], qi[r], v[r].y);
-                                horner_step<R>(ar[r], ai[r], qr[r], qi[r], v[r].x);
-                            }
+                            goertzel_step<R>(b1[r], b2[r], tq2[r], ms, v[r].y);
+                            goertzel_step<R>(b1[r], b2[r], tq2[r], ms, v[r].x);
                         }
                     }
                 }
 #pragma unroll
                 for (int r = 0; r < PPT; ++r) {
-                    // mu = I_0 * acc, Upsilon += gamma Pi e^{i Theta} mu
-                    const R mr = i0r[r] * ar[r] - i0i[r] * ai[r];
-                    const R mi = i0r[r] * ai[r] + i0i[r] * ar[r];
+                    // P(q) = b_0 - conj(q) b_1;  mu = I_0 P;  Upsilon += gamma Pi e^{i Theta} mu
+                    const R pr = b1[r] - qr[r] * b2[r], pi = qi[r] * b2[r];
+                    const R mr = i0r[r] * pr - i0i[r] * pi;
+                    const R mi = i0r[r] * pi + i0i[r] * pr;
                     ur[r] += rr[r] * mr - ri[r] * mi;
                     ui[r] += rr[r] * mi + ri[r] * mr;
                 }
@@ -286,7 +293,7 @@ __global__ void __launch_bounds__(THREADS) region_kernel(RegionArgs a)
 #pragma unroll
             for (int r = 0; r < PPT; ++r) {
                 if (!ok[r]) continue;
-                const int jr = j0 + r0 + 8 * r;
+                const int jr = j0 + lj + 8 * r;
                 const int m = mb + mm[r];
                 const double S2 = a.Sg[jr];
                 const double u2 = (double)ur[r] * (double)ur[r] + (double)ui[r] * (double)ui[r];
@@ -513,10 +520,17 @@ hipError_t launch_region(const RegionArgs& a, int n_items, bool fp32, hipStream_
 {
     const unsigned grid = (unsigned)n_items * (unsigned)a.n_groups;
     if (grid == 0) return hipSuccess;
-    if (fp32)
-        hipLaunchKernelGGL(region_kernel<float>, dim3(grid), dim3(THREADS), 0, st, a);
-    else
-        hipLaunchKernelGGL(region_kernel<double>, dim3(grid), dim3(THREADS), 0, st, a);
+    if (fp32) {
+        if (a.mu_method == 0)
+            hipLaunchKernelGGL((region_kernel<float, 0>), dim3(grid), dim3(THREADS), 0, st, a);
+        else
+            hipLaunchKernelGGL((region_kernel<float, 1>), dim3(grid), dim3(THREADS), 0, st, a);
+    } else {
+        if (a.mu_method == 0)
+            hipLaunchKernelGGL((region_kernel<double, 0>), dim3(grid), dim3(THREADS), 0, st, a);
+        else
+            hipLaunchKernelGGL((region_kernel<double, 1>), dim3(grid), dim3(THREADS), 0, st, a);
+    }
     return hipGetLastError();
 }
 
