@@ -83,14 +83,6 @@ __device__ double block_sum(double v, double* sh)
     return r;
 }
 
-// b_k = g_k + t b_{k+1} - s b_{k+2}  (ms = -s)
-template <typename R>
-__device__ __forceinline__ void goertzel_step(R& b1, R& b2, R t, R ms, R g)
-{
-    const R b0 = fma(ms, b2, fma(t, b1, g));
-    b2 = b1;
-    b1 = b0;
-}
 
 template <typename R, int MU>
 __global__ void __launch_bounds__(THREADS) region_kernel(RegionArgs a)
@@ -262,6 +254,9 @@ __global__ void __launch_bounds__(THREADS) region_kernel(RegionArgs a)
                     // every point reads its own anti-diagonal row: one base index
                     // plus compile-time row offsets (8 rows apart per point)
                     const Vec* gb = g_vec + (li + lj) * KPV;
+                    // two segments per pair of updates: b2 takes b_k, then b1 takes
+                    // b_{k-1}, so the state never moves between registers
+#pragma unroll 2
                     for (int kv = len / VW - 1; kv >= 0; --kv) {
                         Vec v[PPT];
 #pragma unroll
@@ -269,11 +264,11 @@ __global__ void __launch_bounds__(THREADS) region_kernel(RegionArgs a)
 #pragma unroll
                         for (int r = 0; r < PPT; ++r) {
                             if constexpr (VW == 4) {
-                                goertzel_step<R>(b1[r], b2[r], tq2[r], ms, v[r].w);
-                                goertzel_step<R>(b1[r], b2[r], tq2[r], ms, v[r].z);
+                                b2[r] = fma(ms, b2[r], fma(tq2[r], b1[r], v[r].w));
+                                b1[r] = fma(ms, b1[r], fma(tq2[r], b2[r], v[r].z));
                             }
-                            goertzel_step<R>(b1[r], b2[r], tq2[r], ms, v[r].y);
-                            goertzel_step<R>(b1[r], b2[r], tq2[r], ms, v[r].x);
+                            b2[r] = fma(ms, b2[r], fma(tq2[r], b1[r], v[r].y));
+                            b1[r] = fma(ms, b1[r], fma(tq2[r], b2[r], v[r].x));
                         }
                     }
                 }
