@@ -175,6 +175,64 @@ int32_t isrs_eval_islands(isrs_ctx* ctx, const isrs_numerics* numerics, int32_t 
 int32_t isrs_set_profiling(isrs_ctx* ctx, int32_t profile);
 int32_t isrs_get_stats(const isrs_ctx* ctx, isrs_stats* out);
 
+/* ------------------------------------------------------------------------
+ * Batched evaluation of many links in one persistent launch.
+ *
+ * A batch holds n_links independent links (each its own spectrum, span
+ * list and CUT list), concatenated CSR-style.  Evaluation runs every
+ * (link, CUT, channel-pair square) of the batch through one cost-sorted
+ * work queue (the islands are independent: Sec. II-B), captured in a HIP
+ * graph on the first call and replayed by later calls with the same
+ * numerics; other numerics rebuild the work list and re-capture.
+ * ------------------------------------------------------------------------ */
+typedef struct isrs_batch isrs_batch;
+
+typedef struct {
+    int32_t n_links;
+    const int32_t* ch_offset;      /* [n_links+1] link l owns channels ch_offset[l] .. ch_offset[l+1]-1 */
+    const int32_t* span_offset;    /* [n_links+1] link l owns spans span_offset[l] .. span_offset[l+1]-1 */
+    const int32_t* cut_offset;     /* [n_links+1] into cuts, or NULL: every active channel is a CUT */
+    const int32_t* cuts;           /* concatenated CUT channel indices (local to each link), or NULL */
+    const double* spacing_thz;     /* [n_links] */
+    const double* symbol_rate_thz; /* [n_links] */
+    const double* rolloff;         /* [n_links] */
+    const int32_t* gain_mode;      /* [n_links] ISRS_GAIN_*, or NULL for EQUALIZED */
+    const double* power_w;         /* [ch_offset[n_links]] launch powers, 0 = inactive */
+    const double* phi;             /* [ch_offset[n_links]] */
+    const double* psi;             /* [ch_offset[n_links]] */
+    const isrs_span* spans;        /* [span_offset[n_links]] */
+} isrs_link_batch;
+
+/* Validates and deep-copies a batch (host arrays).  Errors: ISRS_E_ARG,
+ * ISRS_E_SPECTRUM / ISRS_E_LINK with the offending link in the message. */
+int32_t isrs_batch_create(isrs_ctx* ctx, const isrs_link_batch* batch, isrs_batch** out);
+int32_t isrs_batch_destroy(isrs_batch* batch);
+
+/* Number of CUTs of the batch (the length of the eta outputs). */
+int32_t isrs_batch_num_cuts(const isrs_batch* batch, int64_t* n_cuts);
+
+/* eta of every CUT of every link (link order, then CUT order), host
+ * [n_cuts] 1/W^2; synchronises the context's stream.  The first call with
+ * given numerics builds the work list and captures a HIP graph; later calls
+ * replay it.  Errors as isrs_eval_eta. */
+int32_t isrs_batch_eval(isrs_ctx* ctx, isrs_batch* batch, const isrs_numerics* numerics, double* eta);
+
+/* As isrs_batch_eval with a device output [n_cuts]; stream-ordered. */
+int32_t isrs_batch_eval_dev(isrs_ctx* ctx, isrs_batch* batch, const isrs_numerics* numerics, double* eta_dev);
+
+/* Launch-shape autotuner: times the candidate region launches (one block per
+ * work unit, or persistent blocks per CU in {1, 2, 3} on the queue; natural
+ * or cost-sorted order; strip grouping) on this batch, keeps the fastest for
+ * the batch, and caches the choice in the JSON file at cache_path (nullable)
+ * keyed by architecture, grid size, segment-count and span-count buckets,
+ * precision and FWM form.  A cached entry is reused without timing. */
+int32_t isrs_autotune(isrs_ctx* ctx, isrs_batch* batch, const isrs_numerics* numerics, const char* cache_path);
+
+/* Launch shape in use on a batch: mode 0 = one block per unit, 1 = queue;
+ * blocks_per_cu, sort (1 = cost-sorted) and strips per unit. */
+int32_t isrs_batch_get_tuning(const isrs_batch* batch, int32_t* mode, int32_t* blocks_per_cu, int32_t* sort,
+                              int32_t* strips);
+
 /* Pure host checks used by the set/eval calls (no device needed). */
 int32_t isrs_validate_spectrum(const isrs_spectrum* spectrum);
 int32_t isrs_validate_link(const isrs_span* spans, int32_t n_spans, int32_t gain_mode);

@@ -33,6 +33,8 @@ EXPORTED = [
     "isrs_set_ptot_override", "isrs_eval_eta", "isrs_eval_eta_dev", "isrs_eval_psd",
     "isrs_eval_islands", "isrs_set_profiling", "isrs_get_stats", "isrs_validate_spectrum",
     "isrs_validate_link", "isrs_validate_numerics", "isrs_version",
+    "isrs_batch_create", "isrs_batch_destroy", "isrs_batch_num_cuts", "isrs_batch_eval",
+    "isrs_batch_eval_dev", "isrs_autotune", "isrs_batch_get_tuning",
 ]
 
 
@@ -57,6 +59,16 @@ class Span_c(C.Structure):
 class Numerics_c(C.Structure):
     _fields_ = [("dz_km", C.c_double), ("n1", C.c_int32), ("n2", C.c_int32), ("n_f", C.c_int32),
                 ("egn", C.c_int32), ("precision", C.c_int32), ("mu_method", C.c_int32)]
+
+
+class LinkBatch_c(C.Structure):
+    _fields_ = [("n_links", C.c_int32), ("ch_offset", C.POINTER(C.c_int32)),
+                ("span_offset", C.POINTER(C.c_int32)), ("cut_offset", C.POINTER(C.c_int32)),
+                ("cuts", C.POINTER(C.c_int32)), ("spacing_thz", C.POINTER(C.c_double)),
+                ("symbol_rate_thz", C.POINTER(C.c_double)), ("rolloff", C.POINTER(C.c_double)),
+                ("gain_mode", C.POINTER(C.c_int32)), ("power_w", C.POINTER(C.c_double)),
+                ("phi", C.POINTER(C.c_double)), ("psi", C.POINTER(C.c_double)),
+                ("spans", C.c_void_p)]
 
 
 class Stats_c(C.Structure):
@@ -99,6 +111,13 @@ def lib():
     L.isrs_validate_numerics.argtypes = [C.POINTER(Numerics_c)]
     L.isrs_version.argtypes = []
     L.isrs_version.restype = C.c_char_p
+    L.isrs_batch_create.argtypes = [vp, C.POINTER(LinkBatch_c), C.POINTER(vp)]
+    L.isrs_batch_destroy.argtypes = [vp]
+    L.isrs_batch_num_cuts.argtypes = [vp, C.POINTER(C.c_int64)]
+    L.isrs_batch_eval.argtypes = [vp, vp, C.POINTER(Numerics_c), dp]
+    L.isrs_batch_eval_dev.argtypes = [vp, vp, C.POINTER(Numerics_c), vp]
+    L.isrs_autotune.argtypes = [vp, vp, C.POINTER(Numerics_c), C.c_char_p]
+    L.isrs_batch_get_tuning.argtypes = [vp, ip, ip, ip, ip]
     for name in EXPORTED:
         f = getattr(L, name)
         if f.restype is C.c_int:  # default
@@ -163,6 +182,96 @@ def validate_link(spans, gain_mode=0):
 def validate_numerics(numerics):
     n = numerics if isinstance(numerics, Numerics_c) else numerics_struct(numerics)
     return lib().isrs_validate_numerics(C.byref(n))
+
+
+class _BatchArgs:
+    """CSR packing of a list of workloads.Workload into isrs_link_batch."""
+
+    def __init__(self, workloads):
+        n = len(workloads)
+        ch, sp, cu = [0], [0], [0]
+        spacing, rs, ro, gm = [], [], [], []
+        power, phi, psi, cuts, spans = [], [], [], [], []
+        for w in workloads:
+            s = w.spectrum
+            power.append(_f64(s.power_w))
+            phi.append(_f64(s.phi))
+            psi.append(_f64(s.psi))
+            ch.append(ch[-1] + int(s.n_ch))
+            spacing.append(s.spacing_thz)
+            rs.append(s.symbol_rate_thz)
+            ro.append(s.rolloff)
+            gm.append(int(w.link.gain_mode))
+            sarr = span_structs(w.link.spans)
+            spans.extend(sarr)
+            sp.append(sp[-1] + len(sarr))
+            c = np.asarray(w.cuts, dtype=np.int32)
+            cuts.append(c)
+            cu.append(cu[-1] + len(c))
+        self.ch = np.asarray(ch, np.int32)
+        self.sp = np.asarray(sp, np.int32)
+        self.cu = np.asarray(cu, np.int32)
+        self.cuts = np.ascontiguousarray(np.concatenate(cuts).astype(np.int32))
+        self.spacing = _f64(spacing)
+        self.rs = _f64(rs)
+        self.ro = _f64(ro)
+        self.gm = np.asarray(gm, np.int32)
+        self.power = _f64(np.concatenate(power))
+        self.phi = _f64(np.concatenate(phi))
+        self.psi = _f64(np.concatenate(psi))
+        self.spans = (Span_c * len(spans))(*spans)
+        self.c = LinkBatch_c(n, _ip(self.ch), _ip(self.sp), _ip(self.cu), _ip(self.cuts), _dp(self.spacing),
+                             _dp(self.rs), _dp(self.ro), _ip(self.gm), _dp(self.power), _dp(self.phi),
+                             _dp(self.psi), C.cast(self.spans, C.c_void_p))
+        self.n_cuts = int(self.cu[-1])
+
+
+class Batch:
+    """Many links evaluated through one work queue (isrs_batch_*)."""
+
+    def __init__(self, engine, workloads):
+        self._e = engine
+        self._args = _BatchArgs(workloads)
+        self._h = C.c_void_p()
+        engine._check(engine._L.isrs_batch_create(engine._h, C.byref(self._args.c), C.byref(self._h)))
+        n = C.c_int64()
+        engine._check(engine._L.isrs_batch_num_cuts(self._h, C.byref(n)))
+        self.n_cuts = int(n.value)
+        self.cut_offset = self._args.cu.copy()
+
+    def close(self):
+        if self._h:
+            self._e._L.isrs_batch_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def eval(self, numerics, **override):
+        nu = numerics if isinstance(numerics, Numerics_c) else numerics_struct(numerics, **override)
+        out = np.zeros(self.n_cuts)
+        self._e._check(self._e._L.isrs_batch_eval(self._e._h, self._h, C.byref(nu), _dp(out)))
+        return out
+
+    def eval_dev(self, numerics, eta_dev, **override):
+        nu = numerics if isinstance(numerics, Numerics_c) else numerics_struct(numerics, **override)
+        if str(eta_dev.dtype) != "torch.float64" or not eta_dev.is_cuda or eta_dev.numel() < self.n_cuts:
+            raise ValueError("eta_dev must be a float64 GPU tensor with n_cuts elements")
+        self._e._check(self._e._L.isrs_batch_eval_dev(self._e._h, self._h, C.byref(nu), C.c_void_p(eta_dev.data_ptr())))
+
+    def autotune(self, numerics, cache_path=None, **override):
+        nu = numerics if isinstance(numerics, Numerics_c) else numerics_struct(numerics, **override)
+        p = cache_path.encode() if cache_path else None
+        self._e._check(self._e._L.isrs_autotune(self._e._h, self._h, C.byref(nu), p))
+        return self.tuning()
+
+    def tuning(self):
+        v = [C.c_int32() for _ in range(4)]
+        self._e._check(self._e._L.isrs_batch_get_tuning(self._h, *[C.byref(x) for x in v]))
+        return {"mode": v[0].value, "blocks_per_cu": v[1].value, "sort": v[2].value, "strips": v[3].value}
 
 
 @dataclass
@@ -276,6 +385,9 @@ class Engine:
         out = np.zeros(m * 15)
         self._check(self._L.isrs_eval_islands(self._h, C.byref(nu), int(cut), _ip(sq), m, _dp(out)))
         return out.reshape(m, 3, 5)
+
+    def batch(self, workloads):
+        return Batch(self, workloads)
 
     def stats(self) -> Stats:
         s = Stats_c()

@@ -2,9 +2,9 @@
 //
 // Validates inputs, builds the per-span segment tables (Eqs. 8-10, 25), the
 // per-anti-diagonal island tables (Eq. 16 on the grid), the f1 <-> f2 folded
-// work list of channel-pair squares, and launches the gfx950 kernels on the
-// context's stream.  No model arithmetic runs on the CPU beyond these tables:
-// every grid point is evaluated on the GPU.
+// work list of channel-pair squares of one or many links, and launches the
+// gfx950 kernels on the context's stream.  No model arithmetic runs on the
+// CPU beyond these tables: every grid point is evaluated on the GPU.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -12,7 +12,11 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <map>
 #include <new>
+#include <numeric>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -27,17 +31,19 @@ constexpr int MAX_SPANS = 4096;
 constexpr int MAX_GRID = 8192;
 constexpr int MAX_NF = 4096;
 constexpr int MAX_CH = 100000;
-constexpr double TIE_TOL = 1e-9;          // island-boundary tie tolerance in grid steps
-constexpr size_t DEFAULT_YCAP = size_t(8) << 30;  // bytes of coherent-sum buffer per launch chunk
+constexpr double TIE_TOL = 1e-9;                   // island-boundary tie tolerance in grid steps
+constexpr size_t DEFAULT_YCAP = size_t(8) << 30;   // coherent-sum buffer per launch chunk, bytes
 
 thread_local std::string g_create_error;
+
+bool is_fin(double x) { return std::isfinite(x); }
 
 struct DevBuf {
     void* p = nullptr;
     size_t cap = 0;
     hipError_t ensure(size_t bytes)
     {
-        if (bytes <= cap) return hipSuccess;
+        if (bytes <= cap && p) return hipSuccess;
         if (p) (void)hipFree(p);
         p = nullptr;
         cap = 0;
@@ -61,7 +67,7 @@ struct HostBuf {
     size_t cap = 0;
     hipError_t ensure(size_t bytes)
     {
-        if (bytes <= cap) return hipSuccess;
+        if (bytes <= cap && p) return hipSuccess;
         if (p) (void)hipHostFree(p);
         p = nullptr;
         cap = 0;
@@ -78,7 +84,74 @@ struct HostBuf {
     }
 };
 
-bool is_fin(double x) { return std::isfinite(x); }
+// One link as the planner sees it (pointers into context or batch storage).
+struct LinkInput {
+    int n_ch = 0;
+    double spacing = 0, rs = 0, rolloff = 0;
+    const double* power = nullptr;
+    const double* phi = nullptr;
+    const double* psi = nullptr;
+    const isrs_span* spans = nullptr;
+    int n_sp = 0;
+    int gain_mode = ISRS_GAIN_EQUALIZED;
+    double ptot_override = 0.0;
+    const int32_t* cuts = nullptr;
+    int n_cut = 0;
+};
+
+// Launch shape of the region kernel.
+struct Tuning {
+    int mode = 0;           // 0: one block per work unit, 1: persistent blocks on a queue
+    int blocks_per_cu = 0;  // queue mode; 0 = as many as fit
+    int sort = 1;           // queue mode: cost-sorted order
+    int spb = 0;            // tile strips per unit; 0 = automatic
+};
+
+// Everything one evaluation uploads and launches.
+struct Plan {
+    int N = 0, n_f = 0, AD = 0, nt = 0, n_groups = 1, spb = 1;
+    bool fp32 = false;
+    int mu_method = 0;
+    std::vector<LinkDesc> links;
+    std::vector<SpanConst> spans;
+    std::vector<SegRow64> seg64;
+    std::vector<SegRow32> seg32;
+    std::vector<double> Sg, wt, s3;
+    std::vector<int> livep;
+    std::vector<double> power, phi, psi;
+    std::vector<InstDesc> insts;
+    std::vector<SquareItem> items;
+    std::vector<double> item_cost;   // per square: live points x (sum K + span count)
+    std::vector<int> chunk_begin;    // square index where each launch chunk starts (+ end)
+    std::vector<int> dlist;          // coherent-sum squares in square order
+    std::vector<int> dchunk_begin;
+    std::vector<int> order;          // per chunk: cost-sorted permutation of its units
+    std::vector<std::vector<long long>> livepts;  // per link: [n_f][8 masks][2N] prefix of live points
+    long long horner_steps = 0, live_points = 0;
+    double alg_flop = 0;
+    int n_cut_total = 0;
+    int queue_blocks = 0;            // persistent blocks of a queue launch
+};
+
+// Device side of a plan.
+struct Workspace {
+    DevBuf links, spans, seg, Sg, wt, s3, livep, insts, items, order, partD, partE, Y, dlist, counter, out,
+        power, phi, psi;
+    HostBuf stage;
+    hipEvent_t ev_upload = nullptr;
+    std::vector<hipEvent_t> ev_pool;
+    void release()
+    {
+        DevBuf* bufs[] = {&links, &spans, &seg, &Sg, &wt, &s3, &livep, &insts, &items, &order, &partD, &partE,
+                          &Y, &dlist, &counter, &out, &power, &phi, &psi};
+        for (DevBuf* b : bufs) b->release();
+        stage.release();
+        if (ev_upload) (void)hipEventDestroy(ev_upload);
+        ev_upload = nullptr;
+        for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+        ev_pool.clear();
+    }
+};
 
 }  // namespace
 
@@ -101,12 +174,9 @@ struct isrs_ctx {
     bool profiling = false;
     isrs_stats stats{};
     size_t ycap = DEFAULT_YCAP;
+    int n_cu = 0;
 
-    DevBuf d_spans, d_seg, d_Sg, d_wt, d_s3, d_livep, d_insts, d_items, d_partD, d_partE, d_Y, d_dlist,
-        d_out, d_power, d_phi, d_psi;
-    HostBuf h_stage;
-    hipEvent_t ev_upload = nullptr;
-    std::vector<hipEvent_t> ev_pool;
+    Workspace* ws = nullptr;
 };
 
 namespace {
@@ -129,25 +199,32 @@ int32_t hip_fail(isrs_ctx* c, hipError_t e, const char* what)
         if (_e != hipSuccess) return hip_fail((ctx), _e, #expr); \
     } while (0)
 
-std::string validate_spectrum_msg(const isrs_spectrum* s)
+std::string validate_spectrum_fields(int n_ch, double spacing, double rs, double ro, const double* power,
+                                     const double* phi, const double* psi)
 {
-    if (!s) return "spectrum is null";
-    if (s->n_ch < 1 || s->n_ch > MAX_CH) return "n_ch out of range";
-    if (!s->power_w || !s->phi || !s->psi) return "spectrum arrays must not be null";
-    if (!(is_fin(s->spacing_thz) && s->spacing_thz > 0)) return "spacing must be finite and > 0";
-    if (!(is_fin(s->symbol_rate_thz) && s->symbol_rate_thz > 0)) return "symbol rate must be finite and > 0";
-    if (!(is_fin(s->rolloff) && s->rolloff >= 0 && s->rolloff <= 1)) return "roll-off must be in [0, 1]";
-    if (!is_fin(s->f_center_thz)) return "f_center must be finite";
-    if ((1.0 + s->rolloff) * s->symbol_rate_thz > s->spacing_thz * (1.0 + 1e-12))
+    if (n_ch < 1 || n_ch > MAX_CH) return "n_ch out of range";
+    if (!power || !phi || !psi) return "spectrum arrays must not be null";
+    if (!(is_fin(spacing) && spacing > 0)) return "spacing must be finite and > 0";
+    if (!(is_fin(rs) && rs > 0)) return "symbol rate must be finite and > 0";
+    if (!(is_fin(ro) && ro >= 0 && ro <= 1)) return "roll-off must be in [0, 1]";
+    if ((1.0 + ro) * rs > spacing * (1.0 + 1e-12))
         return "(1 + rolloff) * symbol rate exceeds the channel spacing (channels would overlap)";
     int active = 0;
-    for (int k = 0; k < s->n_ch; ++k) {
-        if (!(is_fin(s->power_w[k]) && s->power_w[k] >= 0)) return "power must be finite and >= 0";
-        if (!is_fin(s->phi[k]) || !is_fin(s->psi[k])) return "phi / psi must be finite";
-        active += s->power_w[k] > 0;
+    for (int k = 0; k < n_ch; ++k) {
+        if (!(is_fin(power[k]) && power[k] >= 0)) return "power must be finite and >= 0";
+        if (!is_fin(phi[k]) || !is_fin(psi[k])) return "phi / psi must be finite";
+        active += power[k] > 0;
     }
     if (!active) return "no active channel";
     return "";
+}
+
+std::string validate_spectrum_msg(const isrs_spectrum* s)
+{
+    if (!s) return "spectrum is null";
+    if (!is_fin(s->f_center_thz)) return "f_center must be finite";
+    return validate_spectrum_fields(s->n_ch, s->spacing_thz, s->symbol_rate_thz, s->rolloff, s->power_w, s->phi,
+                                    s->psi);
 }
 
 std::string validate_link_msg(const isrs_span* sp, int32_t n, int32_t gain_mode)
@@ -179,6 +256,17 @@ std::string validate_numerics_msg(const isrs_numerics* nu)
     return "";
 }
 
+std::string validate_link_numerics(const LinkInput& L, const isrs_numerics* nu)
+{
+    for (int s = 0; s < L.n_sp; ++s)
+        if (std::ceil(L.spans[s].length_km / nu->dz_km) > 1e6) return "dz too small: more than 1e6 segments";
+    for (int q = 0; q < L.n_cut; ++q) {
+        if (L.cuts[q] < 0 || L.cuts[q] >= L.n_ch) return "CUT index out of range";
+        if (!(L.power[L.cuts[q]] > 0)) return "CUT is an inactive channel";
+    }
+    return "";
+}
+
 // Raised-cosine shape, 1 in the flat part, 0 outside (1+ro) Rs / 2.
 double rc(double x, double rs, double ro)
 {
@@ -190,144 +278,131 @@ double rc(double x, double rs, double ro)
 
 double field_S(double x, double rs, double ro) { return std::sqrt(rc(x, rs, ro)) / rs; }
 
-struct Plan {
-    int N, n_f, AD, nt, n_groups, spb;
-    double W, h, B, ptot;
-    bool fp32;
-    std::vector<SpanConst> spans;
-    std::vector<SegRow64> seg64;
-    std::vector<SegRow32> seg32;
-    std::vector<double> Sg, wt, s3, fs;
-    std::vector<int> livep;
-    std::vector<long long> livepts;  // [n_f][8 masks][2N] prefix of points on live anti-diagonals
-    std::vector<InstDesc> insts;
-    std::vector<SquareItem> items;
-    std::vector<int> chunk_begin;    // item index where each launch chunk starts (+ end)
-    std::vector<int> dlist;          // coherent-sum squares in item order
-    std::vector<int> dchunk_begin;
-    long long horner_steps = 0, live_points = 0;
-    double alg_flop = 0;
-    int sumK = 0;
-};
-
-// Tables of Eqs. 8-10 / 25 per span, island tables per outer sample.
-void build_tables(const isrs_ctx* c, const isrs_numerics* nu, Plan& p)
+void plan_begin(const isrs_numerics* nu, Plan& p)
 {
     p.N = nu->n1;
     p.n_f = nu->n_f;
     p.AD = 2 * p.N - 1;
-    p.W = (1.0 + c->rolloff) * c->rs;
-    p.h = p.W / p.N;
-    p.B = c->n_ch * c->spacing;
-    double pt = 0.0;
-    for (double x : c->power) pt += x;
-    p.ptot = c->ptot_override > 0 ? c->ptot_override : pt;
+    p.nt = (p.N + TILE - 1) / TILE;
     p.fp32 = nu->precision == ISRS_PREC_FP32_PHASE64;
+    p.mu_method = nu->mu_method;
+}
 
-    const int ns = (int)c->spans.size();
-    p.spans.resize(ns);
+// Tables of one link (Eqs. 8-10 / 25 per span, islands per outer sample).
+void plan_link_tables(const LinkInput& L, const isrs_numerics* nu, Plan& p)
+{
+    LinkDesc d{};
+    const double W = (1.0 + L.rolloff) * L.rs, h = W / p.N, B = L.n_ch * L.spacing;
+    double pt = 0.0;
+    for (int k = 0; k < L.n_ch; ++k) pt += L.power[k];
+    const double ptot = L.ptot_override > 0 ? L.ptot_override : pt;
+    d.span0 = (int)p.spans.size();
+    d.n_sp = L.n_sp;
+    d.n_ch = L.n_ch;
+    d.gain_mode = L.gain_mode;
+    d.ch0 = (int)p.power.size();
+    d.spacing = L.spacing;
+    d.h = h;
+    d.rs = L.rs;
+    p.power.insert(p.power.end(), L.power, L.power + L.n_ch);
+    p.phi.insert(p.phi.end(), L.phi, L.phi + L.n_ch);
+    p.psi.insert(p.psi.end(), L.psi, L.psi + L.n_ch);
+
     // LOSS_ONLY gain: per span A(L) and zeta(L) of rho(L, x) = A e^{-zeta x} e^{-alpha L}
-    std::vector<double> lnA(ns), zL(ns);
+    std::vector<double> lnA(L.n_sp), zL(L.n_sp);
     double b2L = 0.0, b3L = 0.0;
-    int off = 0;
-    p.seg64.clear();
-    for (int s = 0; s < ns; ++s) {
-        const isrs_span& sp = c->spans[s];
+    for (int s = 0; s < L.n_sp; ++s) {
+        const isrs_span& sp = L.spans[s];
         const double alpha = sp.alpha_db_km * std::log(10.0) / 10.0;
-        const double L = sp.length_km;
-        int K = (int)std::ceil(L / nu->dz_km);
+        const double len = sp.length_km;
+        int K = (int)std::ceil(len / nu->dz_km);
         if (K < 1) K = 1;
-        const double dl = L / K;
-        SpanConst& q = p.spans[s];
+        const double dl = len / K;
+        SpanConst q{};
         q.c2r = 2.0 * M_PI * sp.beta2_ps2_km * dl;
         q.c3r = 2.0 * M_PI * M_PI * sp.beta3_ps3_km * dl;
         q.c2x = 4.0 * M_PI * M_PI * sp.beta2_ps2_km;
         q.c3x = 4.0 * M_PI * M_PI * M_PI * sp.beta3_ps3_km;
         q.p2r = 2.0 * M_PI * b2L;
         q.p3r = 2.0 * M_PI * M_PI * b3L;
-        q.c2L = 2.0 * M_PI * sp.beta2_ps2_km * L;
-        q.c3L = 2.0 * M_PI * M_PI * sp.beta3_ps3_km * L;
+        q.c2L = 2.0 * M_PI * sp.beta2_ps2_km * len;
+        q.c3L = 2.0 * M_PI * M_PI * sp.beta3_ps3_km * len;
         q.em = std::exp(-alpha * dl);
-        q.emL = std::exp(-alpha * L);
-        q.em2L = std::exp(-2.0 * alpha * L);
+        q.emL = std::exp(-alpha * len);
+        q.em2L = std::exp(-2.0 * alpha * len);
         q.alpha = alpha;
         q.gamma = sp.gamma_w_km;
-        q.pcr = p.ptot * sp.cr_w_km_thz;
+        q.pcr = ptot * sp.cr_w_km_thz;
         q.K = K;
-        q.off = off;
-        b2L += sp.beta2_ps2_km * L;
-        b3L += sp.beta3_ps3_km * L;
+        q.off = (int)p.seg64.size();
+        b2L += sp.beta2_ps2_km * len;
+        b3L += sp.beta3_ps3_km * len;
         for (int k = 0; k < K; ++k) {
-            const double z = (k + 0.5) / K * L;
+            const double z = (k + 0.5) / K * len;
             const double leff = -std::expm1(-alpha * z) / alpha;
-            const double X = p.B * p.ptot * sp.cr_w_km_thz * leff;
+            const double X = B * ptot * sp.cr_w_km_thz * leff;
             const double A = X == 0.0 ? 1.0 : X / (2.0 * std::sinh(0.5 * X));
-            const double zeta = X / p.B;
-            p.seg64.push_back({A, zeta, std::exp(-zeta * p.h), 0.0});
+            const double zeta = X / B;
+            p.seg64.push_back({A, zeta, std::exp(-zeta * h), 0.0});
         }
-        const double leffL = -std::expm1(-alpha * L) / alpha;
-        const double XL = p.B * p.ptot * sp.cr_w_km_thz * leffL;
+        const double leffL = -std::expm1(-alpha * len) / alpha;
+        const double XL = B * ptot * sp.cr_w_km_thz * leffL;
         lnA[s] = XL == 0.0 ? 0.0 : std::log(XL / (2.0 * std::sinh(0.5 * XL)));
-        zL[s] = XL / p.B;
-        off += K;
+        zL[s] = XL / B;
+        p.spans.push_back(q);
     }
-    p.sumK = off;
-    double TA = 0.0, TZ = 0.0;
-    for (int s = 0; s < ns; ++s) {
+    double TA = 0.0, TZ = 0.0, PA = 0.0, PZ = 0.0;
+    for (int s = 0; s < L.n_sp; ++s) {
         TA += lnA[s];
         TZ += zL[s];
     }
-    double PA = 0.0, PZ = 0.0;
-    for (int s = 0; s < ns; ++s) {
+    for (int s = 0; s < L.n_sp; ++s) {
         // ln Pi_s = sum_{s'<s} [1.5 lnA - 0.5 zeta (a + b + x3)] + sum_{s'>=s} [0.5 lnA - 0.5 zeta c],
         // with a + b + x3 = 2 (a + b) - c
-        p.spans[s].pi_a = PA + 0.5 * TA;
-        p.spans[s].pi_s = PZ;
-        p.spans[s].pi_c = PZ - 0.5 * TZ;
+        SpanConst& q = p.spans[d.span0 + s];
+        q.pi_a = PA + 0.5 * TA;
+        q.pi_s = PZ;
+        q.pi_c = PZ - 0.5 * TZ;
         PA += lnA[s];
         PZ += zL[s];
     }
-    p.seg32.resize(p.seg64.size());
-    for (size_t i = 0; i < p.seg64.size(); ++i)
-        p.seg32[i] = {(float)p.seg64[i].A, (float)p.seg64[i].zeta, (float)p.seg64[i].ratio, 0.0f};
 
-    // S at the grid points of a channel
-    p.Sg.resize(p.N);
-    for (int i = 0; i < p.N; ++i) p.Sg[i] = field_S((i + 0.5 - 0.5 * p.N) * p.h, c->rs, c->rolloff);
+    d.sg0 = (int)p.Sg.size();
+    for (int i = 0; i < p.N; ++i) p.Sg.push_back(field_S((i + 0.5 - 0.5 * p.N) * h, L.rs, L.rolloff));
 
-    // outer samples and island tables
-    p.fs.resize(p.n_f);
-    for (int n = 0; n < p.n_f; ++n) p.fs[n] = p.n_f == 1 ? 0.0 : -0.5 * c->rs + (n + 0.5) * c->rs / p.n_f;
     const int AD = p.AD;
-    p.wt.assign((size_t)p.n_f * 3 * AD, 0.0);
-    p.s3.assign((size_t)p.n_f * 3 * AD, 0.0);
-    p.livep.assign((size_t)p.n_f * 3 * (AD + 1), 0);
-    p.livepts.assign((size_t)p.n_f * 8 * (AD + 1), 0);
-    const double ratio = c->spacing / p.h, half = 0.5 * p.N;
+    d.tab0 = (int)p.wt.size();
+    d.livep0 = (int)p.livep.size();
+    p.wt.resize(p.wt.size() + (size_t)p.n_f * 3 * AD, 0.0);
+    p.s3.resize(p.s3.size() + (size_t)p.n_f * 3 * AD, 0.0);
+    p.livep.resize(p.livep.size() + (size_t)p.n_f * 3 * (AD + 1), 0);
+    std::vector<long long> lpts((size_t)p.n_f * 8 * (AD + 1), 0);
+    const double ratio = L.spacing / h, half = 0.5 * p.N;
     for (int n = 0; n < p.n_f; ++n) {
-        const double f = p.fs[n];
+        const double f = p.n_f == 1 ? 0.0 : -0.5 * L.rs + (n + 0.5) * L.rs / p.n_f;
         std::vector<unsigned char> liv(3 * AD, 0);
         for (int l = 0; l < 3; ++l) {
+            int* lp = &p.livep[d.livep0 + ((size_t)n * 3 + l) * (AD + 1)];
             for (int m = 0; m < AD; ++m) {
-                const double u = (double)(m + 1 - p.N) - f / p.h - (l - 1) * ratio;  // f3 / h
+                const double u = (double)(m + 1 - p.N) - f / h - (l - 1) * ratio;  // f3 / h
                 const double au = std::fabs(u);
                 double w = 0.0, sv = 0.0;
                 if (au < half - TIE_TOL) {
                     w = 1.0;
-                    sv = field_S(u * p.h, c->rs, c->rolloff);
+                    sv = field_S(u * h, L.rs, L.rolloff);
                 } else if (au <= half + TIE_TOL) {
                     w = 0.5;  // boundary: the cell is split between two islands
-                    sv = c->rolloff == 0.0 ? 1.0 / c->rs : field_S(u * p.h, c->rs, c->rolloff);
+                    sv = L.rolloff == 0.0 ? 1.0 / L.rs : field_S(u * h, L.rs, L.rolloff);
                 }
-                const size_t o = ((size_t)n * 3 + l) * AD + m;
+                const size_t o = d.tab0 + ((size_t)n * 3 + l) * AD + m;
                 p.wt[o] = w;
                 p.s3[o] = sv;
                 liv[l * AD + m] = (w > 0.0 && sv != 0.0);
-                p.livep[((size_t)n * 3 + l) * (AD + 1) + m + 1] = p.livep[((size_t)n * 3 + l) * (AD + 1) + m] + liv[l * AD + m];
+                lp[m + 1] = lp[m] + liv[l * AD + m];
             }
         }
         for (int mask = 0; mask < 8; ++mask) {
-            long long* pp = &p.livepts[((size_t)n * 8 + mask) * (AD + 1)];
+            long long* pp = &lpts[((size_t)n * 8 + mask) * (AD + 1)];
             for (int m = 0; m < AD; ++m) {
                 bool any = false;
                 for (int l = 0; l < 3; ++l) any |= ((mask >> l) & 1) && liv[l * AD + m];
@@ -336,32 +411,34 @@ void build_tables(const isrs_ctx* c, const isrs_numerics* nu, Plan& p)
             }
         }
     }
-    p.nt = (p.N + TILE - 1) / TILE;
+    p.livepts.push_back(std::move(lpts));
+    p.links.push_back(d);
 }
 
-// Work list over (CUT, f sample) instances and their folded squares.
-void build_work(const isrs_ctx* c, const isrs_numerics* nu, const int32_t* cuts, int n_cut,
-                const int32_t* kappa12, int m_explicit, size_t ycap, Plan& p)
+// Instances and folded squares of one link's CUTs.
+void plan_link_work(const LinkInput& L, int link, const isrs_numerics* nu, const int32_t* kappa12, int m_explicit,
+                    Plan& p)
 {
-    const int nc = c->n_ch, AD = p.AD;
-    p.insts.clear();
-    p.items.clear();
-    p.dlist.clear();
-    const size_t ybytes = (size_t)p.N * p.N * (p.fp32 ? 8 : 16);
+    const int nc = L.n_ch, AD = p.AD;
+    const LinkDesc& d = p.links[link];
     const bool explicit_sq = kappa12 != nullptr;
     double ksum = 0.0;
-    for (const SpanConst& s : p.spans) ksum += 8.0 * s.K + 30.0;
     long long steps_per_point = 0;
-    for (const SpanConst& s : p.spans) steps_per_point += s.K;
-    for (int q = 0; q < n_cut; ++q) {
-        const int cut = cuts[q];
+    for (int s = 0; s < d.n_sp; ++s) {
+        ksum += 8.0 * p.spans[d.span0 + s].K + 30.0;
+        steps_per_point += p.spans[d.span0 + s].K;
+    }
+    const double unit_cost = (double)steps_per_point + 15.0 * d.n_sp;
+    for (int q = 0; q < L.n_cut; ++q) {
+        const int cut = L.cuts[q];
         for (int n = 0; n < p.n_f; ++n) {
-            InstDesc in;
-            in.f = p.fs[n];
+            InstDesc in{};
+            in.f = p.n_f == 1 ? 0.0 : -0.5 * L.rs + (n + 0.5) * L.rs / p.n_f;
+            in.link = link;
             in.cut = cut;
             in.nf_idx = n;
             in.sq_begin = (int)p.items.size();
-            const int* lp = &p.livep[(size_t)n * 3 * (AD + 1)];
+            const int* lp = &p.livep[d.livep0 + (size_t)n * 3 * (AD + 1)];
             int any_live[3];
             for (int l = 0; l < 3; ++l) any_live[l] = lp[l * (AD + 1) + AD] > 0;
             const int n_sq = explicit_sq ? m_explicit : nc * nc;
@@ -375,22 +452,18 @@ void build_work(const isrs_ctx* c, const isrs_numerics* nu, const int32_t* cuts,
                     k2 = t % nc;
                     if (k2 < k1) continue;  // f1 <-> f2 symmetry: the mirror is folded in
                 }
-                if (!(c->power[k1] > 0 && c->power[k2] > 0)) {
-                    if (!explicit_sq) continue;
-                }
+                const bool pair_active = L.power[k1] > 0 && L.power[k2] > 0;
+                if (!pair_active && !explicit_sq) continue;
                 SquareItem it{};
                 it.inst = (int)p.insts.size();
                 it.k1 = k1;
                 it.k2 = k2;
-                it.lmask = 0;
-                it.egn_mask = 0;
                 it.y_slot = -1;
                 it.d_index = -1;
                 it.mult = explicit_sq ? 1.0f : (k1 < k2 ? 2.0f : 1.0f);
-                const bool pair_active = c->power[k1] > 0 && c->power[k2] > 0;
                 for (int l = -1; l <= 1; ++l) {
                     const int k3 = k1 + k2 - cut + l;
-                    if (!pair_active || k3 < 0 || k3 >= nc || !(c->power[k3] > 0) || !any_live[l + 1]) continue;
+                    if (!pair_active || k3 < 0 || k3 >= nc || !(L.power[k3] > 0) || !any_live[l + 1]) continue;
                     it.lmask |= 1 << (l + 1);
                     if (explicit_sq) {
                         it.egn_mask |= 0xF << (4 * (l + 1));
@@ -402,23 +475,36 @@ void build_work(const isrs_ctx* c, const isrs_numerics* nu, const int32_t* cuts,
                     }
                 }
                 if (it.lmask == 0 && !explicit_sq) continue;
-                const long long pts = p.livepts[((size_t)n * 8 + it.lmask) * (AD + 1) + AD];
+                const long long pts = p.livepts[link][((size_t)n * 8 + it.lmask) * (AD + 1) + AD];
                 p.live_points += pts;
                 p.horner_steps += pts * steps_per_point;
                 p.alg_flop += (double)pts * ksum;
                 p.items.push_back(it);
+                p.item_cost.push_back((double)pts * unit_cost + 1.0);
             }
             in.sq_end = (int)p.items.size();
             p.insts.push_back(in);
         }
+        p.n_cut_total++;
     }
-    // launch chunks: bound the coherent-sum buffer of each chunk by ycap
+}
+
+// Launch chunks (bounded coherent-sum buffer), strip grouping and queue order.
+void plan_finish(Plan& p, size_t ycap, const Tuning& tu)
+{
+    p.seg32.resize(p.seg64.size());
+    for (size_t i = 0; i < p.seg64.size(); ++i)
+        p.seg32[i] = {(float)p.seg64[i].A, (float)p.seg64[i].zeta, (float)p.seg64[i].ratio, 0.0f};
+    const size_t ybytes = (size_t)p.N * p.N * (p.fp32 ? 8 : 16);
     const size_t per_chunk = std::max<size_t>(1, ycap / std::max<size_t>(ybytes, 1));
     p.chunk_begin.assign(1, 0);
     p.dchunk_begin.assign(1, 0);
+    p.dlist.clear();
     size_t slots = 0;
     for (size_t i = 0; i < p.items.size(); ++i) {
         SquareItem& it = p.items[i];
+        it.y_slot = -1;
+        it.d_index = -1;
         if (it.egn_mask == 0) continue;
         if (slots == per_chunk) {
             p.chunk_begin.push_back((int)i);
@@ -431,25 +517,24 @@ void build_work(const isrs_ctx* c, const isrs_numerics* nu, const int32_t* cuts,
     }
     p.chunk_begin.push_back((int)p.items.size());
     p.dchunk_begin.push_back((int)p.dlist.size());
-    // strip groups: enough blocks to fill the chip, few partials
+    // strip groups: by default enough units to fill the chip with few partials
     const long long n_items = (long long)p.items.size();
-    const long long target = 32768;
-    int spb = (int)std::min<long long>(p.nt, std::max<long long>(1, n_items * p.nt / target));
+    int spb = tu.spb > 0 ? std::min(tu.spb, p.nt)
+                         : (int)std::min<long long>(p.nt, std::max<long long>(1, n_items * p.nt / 32768));
     p.spb = spb;
     p.n_groups = (p.nt + spb - 1) / spb;
-}
-
-template <typename T>
-int32_t upload(isrs_ctx* c, DevBuf& d, const std::vector<T>& v, char*& stage)
-{
-    const size_t bytes = v.size() * sizeof(T);
-    HIP_TRY(c, d.ensure(bytes));
-    if (bytes) {
-        std::memcpy(stage, v.data(), bytes);
-        HIP_TRY(c, hipMemcpyAsync(d.p, stage, bytes, hipMemcpyHostToDevice, c->stream));
-        stage += (bytes + 255) & ~size_t(255);
+    // queue order per chunk: longest units first (their cost splits evenly over groups)
+    const size_t n_units = p.items.size() * p.n_groups;
+    p.order.resize(n_units);
+    std::iota(p.order.begin(), p.order.end(), 0);
+    if (tu.mode == 1 && tu.sort) {
+        for (size_t ch = 0; ch + 1 < p.chunk_begin.size(); ++ch) {
+            const size_t b = (size_t)p.chunk_begin[ch] * p.n_groups, e = (size_t)p.chunk_begin[ch + 1] * p.n_groups;
+            std::stable_sort(p.order.begin() + b, p.order.begin() + e, [&](int x, int y) {
+                return p.item_cost[x / p.n_groups] > p.item_cost[y / p.n_groups];
+            });
+        }
     }
-    return ISRS_OK;
 }
 
 template <typename T>
@@ -458,19 +543,266 @@ size_t staged(const std::vector<T>& v)
     return (v.size() * sizeof(T) + 255) & ~size_t(255);
 }
 
-hipEvent_t pool_event(isrs_ctx* c, size_t i)
+template <typename T>
+int32_t upload(isrs_ctx* c, hipStream_t st, DevBuf& d, const std::vector<T>& v, char*& stage)
 {
-    while (c->ev_pool.size() <= i) {
-        hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) return nullptr;
-        c->ev_pool.push_back(e);
+    const size_t bytes = v.size() * sizeof(T);
+    HIP_TRY(c, d.ensure(bytes));
+    if (bytes) {
+        std::memcpy(stage, v.data(), bytes);
+        HIP_TRY(c, hipMemcpyAsync(d.p, stage, bytes, hipMemcpyHostToDevice, st));
+        stage += (bytes + 255) & ~size_t(255);
     }
-    return c->ev_pool[i];
+    return ISRS_OK;
 }
 
-// Shared evaluation path.  Outputs are device pointers (eta, sigma2, terms,
-// psd nullable except eta); partials_host receives island partials for the
-// explicit-square mode.
+// Host-side consistency of the tables the kernels index (every row a kernel
+// can address must exist in the uploaded arrays).
+std::string plan_check(const Plan& p)
+{
+    size_t rows = 0;
+    for (const SpanConst& q : p.spans) rows = std::max<size_t>(rows, (size_t)q.off + q.K);
+    if ((p.fp32 ? p.seg32.size() : p.seg64.size()) < rows) return "segment table shorter than the spans need";
+    const size_t AD = p.AD;
+    for (const LinkDesc& d : p.links) {
+        if ((size_t)d.span0 + d.n_sp > p.spans.size()) return "span range out of bounds";
+        if ((size_t)d.tab0 + (size_t)p.n_f * 3 * AD > p.wt.size() || p.wt.size() != p.s3.size())
+            return "island table out of bounds";
+        if ((size_t)d.livep0 + (size_t)p.n_f * 3 * (AD + 1) > p.livep.size()) return "live table out of bounds";
+        if ((size_t)d.sg0 + p.N > p.Sg.size()) return "grid table out of bounds";
+        if ((size_t)d.ch0 + d.n_ch > p.power.size()) return "channel table out of bounds";
+    }
+    for (const InstDesc& in : p.insts)
+        if (in.link < 0 || in.link >= (int)p.links.size() || in.sq_begin < 0 || in.sq_end > (int)p.items.size() ||
+            in.nf_idx < 0 || in.nf_idx >= p.n_f)
+            return "instance out of bounds";
+    for (const SquareItem& it : p.items) {
+        if (it.inst < 0 || it.inst >= (int)p.insts.size()) return "square instance out of bounds";
+        const LinkDesc& d = p.links[p.insts[it.inst].link];
+        if (it.k1 < 0 || it.k2 < 0 || it.k1 >= d.n_ch || it.k2 >= d.n_ch) return "square channel out of bounds";
+    }
+    if (p.order.size() != p.items.size() * (size_t)p.n_groups) return "queue order has the wrong length";
+    return "";
+}
+
+// Persistent grid of a queue launch (occupancy query: never inside a capture).
+void plan_queue_shape(const isrs_ctx* c, const Tuning& tu, Plan& p)
+{
+    p.queue_blocks = 0;
+    if (tu.mode != 1) return;
+    const int per_cu = region_blocks_per_cu(p.fp32, p.mu_method);
+    p.queue_blocks = std::max(1, c->n_cu) * (tu.blocks_per_cu > 0 ? std::min(tu.blocks_per_cu, per_cu) : per_cu);
+}
+
+int32_t plan_upload(isrs_ctx* c, Workspace& w, const Plan& p, hipStream_t st)
+{
+    const std::string bad = plan_check(p);
+    if (!bad.empty()) return fail(c, ISRS_E_ARG, "internal plan check: " + bad);
+    if (w.ev_upload) HIP_TRY(c, hipEventSynchronize(w.ev_upload));  // previous copies out of staging
+    const size_t need = staged(p.links) + staged(p.spans) + (p.fp32 ? staged(p.seg32) : staged(p.seg64)) +
+                        staged(p.Sg) + staged(p.wt) + staged(p.s3) + staged(p.livep) + staged(p.insts) +
+                        staged(p.items) + staged(p.dlist) + staged(p.order) + staged(p.power) + staged(p.phi) +
+                        staged(p.psi);
+    HIP_TRY(c, w.stage.ensure(need));
+    char* stage = reinterpret_cast<char*>(w.stage.p);
+    int32_t rc;
+    if ((rc = upload(c, st, w.links, p.links, stage))) return rc;
+    if ((rc = upload(c, st, w.spans, p.spans, stage))) return rc;
+    if (p.fp32) {
+        if ((rc = upload(c, st, w.seg, p.seg32, stage))) return rc;
+    } else {
+        if ((rc = upload(c, st, w.seg, p.seg64, stage))) return rc;
+    }
+    if ((rc = upload(c, st, w.Sg, p.Sg, stage))) return rc;
+    if ((rc = upload(c, st, w.wt, p.wt, stage))) return rc;
+    if ((rc = upload(c, st, w.s3, p.s3, stage))) return rc;
+    if ((rc = upload(c, st, w.livep, p.livep, stage))) return rc;
+    if ((rc = upload(c, st, w.insts, p.insts, stage))) return rc;
+    if ((rc = upload(c, st, w.items, p.items, stage))) return rc;
+    if ((rc = upload(c, st, w.dlist, p.dlist, stage))) return rc;
+    if ((rc = upload(c, st, w.order, p.order, stage))) return rc;
+    if ((rc = upload(c, st, w.power, p.power, stage))) return rc;
+    if ((rc = upload(c, st, w.phi, p.phi, stage))) return rc;
+    if ((rc = upload(c, st, w.psi, p.psi, stage))) return rc;
+    if (!w.ev_upload) HIP_TRY(c, hipEventCreateWithFlags(&w.ev_upload, hipEventDisableTiming));
+    HIP_TRY(c, hipEventRecord(w.ev_upload, st));
+
+    HIP_TRY(c, w.partD.ensure(std::max<size_t>(1, p.items.size()) * p.n_groups * 3 * sizeof(double)));
+    HIP_TRY(c, w.partE.ensure(std::max<size_t>(1, p.dlist.size()) * 12 * sizeof(double)));
+    size_t max_slots = 0;
+    for (size_t ch = 0; ch + 1 < p.dchunk_begin.size(); ++ch)
+        max_slots = std::max<size_t>(max_slots, p.dchunk_begin[ch + 1] - p.dchunk_begin[ch]);
+    const size_t ybytes = (size_t)p.N * p.N * (p.fp32 ? 8 : 16);
+    HIP_TRY(c, w.Y.ensure(std::max<size_t>(1, max_slots) * ybytes));
+    HIP_TRY(c, w.counter.ensure(sizeof(int) * std::max<size_t>(1, p.chunk_begin.size())));
+    return ISRS_OK;
+}
+
+hipEvent_t pool_event(Workspace& w, size_t i)
+{
+    while (w.ev_pool.size() <= i) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        w.ev_pool.push_back(e);
+    }
+    return w.ev_pool[i];
+}
+
+struct Timings {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> reg, egn, asm_;
+};
+
+// Stream-ordered launches of a plan (graph-capturable when timing is off).
+int32_t plan_enqueue(isrs_ctx* c, Workspace& w, const Plan& p, const Tuning& tu, hipStream_t st, double* eta_d,
+                     double* s2_d, double* terms_d, double* psd_d, bool assemble, Timings* tm)
+{
+    RegionArgs ra{};
+    ra.links = w.links.as<LinkDesc>();
+    ra.spans = w.spans.as<SpanConst>();
+    ra.seg = w.seg.p;
+    ra.Sg = w.Sg.as<double>();
+    ra.wt = w.wt.as<double>();
+    ra.s3 = w.s3.as<double>();
+    ra.livep = w.livep.as<int>();
+    ra.insts = w.insts.as<InstDesc>();
+    ra.items = w.items.as<SquareItem>();
+    ra.partD = w.partD.as<double>();
+    ra.ybuf = w.Y.p;
+    ra.n_groups = p.n_groups;
+    ra.spb = p.spb;
+    ra.nt = p.nt;
+    ra.N = p.N;
+    ra.mu_method = p.mu_method;
+    int blocks = 0;
+    if (tu.mode == 1) {
+        blocks = p.queue_blocks;  // fixed at plan time, outside any stream capture
+        ra.order = w.order.as<int>();
+    }
+
+    EgnArgs ea{};
+    ea.links = ra.links;
+    ea.Sg = ra.Sg;
+    ea.wt = ra.wt;
+    ea.s3 = ra.s3;
+    ea.insts = ra.insts;
+    ea.items = ra.items;
+    ea.ybuf = w.Y.p;
+    ea.partE = w.partE.as<double>();
+    ea.N = p.N;
+
+    size_t ev_i = 0;
+    using EvList = std::vector<std::pair<hipEvent_t, hipEvent_t>>;
+    auto mark = [&](EvList* v, bool begin) -> int32_t {
+        if (!v) return ISRS_OK;
+        hipEvent_t e = pool_event(w, ev_i++);
+        if (!e) return fail(c, ISRS_E_DEVICE, "event creation failed");
+        HIP_TRY(c, hipEventRecord(e, st));
+        if (begin)
+            v->push_back({e, nullptr});
+        else
+            v->back().second = e;
+        return ISRS_OK;
+    };
+    EvList* ev_reg = tm ? &tm->reg : nullptr;
+    EvList* ev_egn = tm ? &tm->egn : nullptr;
+    EvList* ev_asm = tm ? &tm->asm_ : nullptr;
+    int32_t rc;
+    const size_t n_chunks = p.chunk_begin.size() - 1;
+    for (size_t ch = 0; ch < n_chunks; ++ch) {
+        const int b = p.chunk_begin[ch], e = p.chunk_begin[ch + 1];
+        ra.unit0 = b * p.n_groups;
+        ra.n_units = (e - b) * p.n_groups;
+        if (tu.mode == 1) {
+            ra.counter = w.counter.as<int>() + ch;
+            HIP_TRY(c, launch_zero_counter(ra.counter, st));
+        }
+        if ((rc = mark(ev_reg, true))) return rc;
+        HIP_TRY(c, launch_region(ra, blocks, p.fp32, st));
+        if ((rc = mark(ev_reg, false))) return rc;
+        const int db = p.dchunk_begin[ch], de = p.dchunk_begin[ch + 1];
+        if (de > db) {
+            ea.dlist = w.dlist.as<int>() + db;
+            if ((rc = mark(ev_egn, true))) return rc;
+            HIP_TRY(c, launch_egn(ea, de - db, p.fp32, st));
+            if ((rc = mark(ev_egn, false))) return rc;
+        }
+    }
+    if (assemble) {
+        AssembleArgs aa{};
+        aa.links = ra.links;
+        aa.insts = ra.insts;
+        aa.items = ra.items;
+        aa.partD = ra.partD;
+        aa.partE = ea.partE;
+        aa.power = w.power.as<double>();
+        aa.phi = w.phi.as<double>();
+        aa.psi = w.psi.as<double>();
+        aa.eta = eta_d;
+        aa.sigma2 = s2_d;
+        aa.terms = terms_d;
+        aa.psd = psd_d;
+        aa.n_groups = p.n_groups;
+        aa.n_f = p.n_f;
+        aa.n_cut = p.n_cut_total;
+        if ((rc = mark(ev_asm, true))) return rc;
+        HIP_TRY(c, launch_assemble(aa, st));
+        if ((rc = mark(ev_asm, false))) return rc;
+    }
+    return ISRS_OK;
+}
+
+int32_t collect_timings(isrs_ctx* c, Timings& tm)
+{
+    auto sum = [&](std::vector<std::pair<hipEvent_t, hipEvent_t>>& v, double& out) -> int32_t {
+        out = 0;
+        for (auto& e : v) {
+            HIP_TRY(c, hipEventSynchronize(e.second));
+            float ms = 0;
+            HIP_TRY(c, hipEventElapsedTime(&ms, e.first, e.second));
+            out += ms;
+        }
+        return ISRS_OK;
+    };
+    int32_t rc;
+    if ((rc = sum(tm.reg, c->stats.region_ms))) return rc;
+    if ((rc = sum(tm.egn, c->stats.egn_ms))) return rc;
+    if ((rc = sum(tm.asm_, c->stats.assemble_ms))) return rc;
+    return ISRS_OK;
+}
+
+void record_stats(isrs_ctx* c, const Plan& p, double host_ms, bool timed)
+{
+    c->stats.host_prep_ms = host_ms;
+    c->stats.region_launches = (int64_t)(p.chunk_begin.size() - 1);
+    c->stats.n_squares = (int64_t)p.items.size();
+    c->stats.n_delta_squares = (int64_t)p.dlist.size();
+    c->stats.n_points_live = p.live_points;
+    c->stats.horner_steps = p.mu_method == ISRS_MU_SEGMENT ? p.horner_steps : 0;
+    c->stats.alg_flop = p.alg_flop;
+    if (!timed) c->stats.region_ms = c->stats.egn_ms = c->stats.assemble_ms = 0;
+}
+
+LinkInput ctx_link(const isrs_ctx* c, const int32_t* cuts, int n_cut)
+{
+    LinkInput L;
+    L.n_ch = c->n_ch;
+    L.spacing = c->spacing;
+    L.rs = c->rs;
+    L.rolloff = c->rolloff;
+    L.power = c->power.data();
+    L.phi = c->phi.data();
+    L.psi = c->psi.data();
+    L.spans = c->spans.data();
+    L.n_sp = (int)c->spans.size();
+    L.gain_mode = c->gain_mode;
+    L.ptot_override = c->ptot_override;
+    L.cuts = cuts;
+    L.n_cut = n_cut;
+    return L;
+}
+
+// Single-link evaluation on the context's workspace.  Outputs are device
+// pointers; partials_host receives island partials in explicit-square mode.
 int32_t evaluate(isrs_ctx* c, const isrs_numerics* nu, const int32_t* cuts, int n_cut, const int32_t* kappa12,
                  int m_explicit, double* eta_d, double* s2_d, double* terms_d, double* psd_d,
                  double* partials_host)
@@ -481,173 +813,39 @@ int32_t evaluate(isrs_ctx* c, const isrs_numerics* nu, const int32_t* cuts, int 
     std::string m = validate_numerics_msg(nu);
     if (!m.empty()) return fail(c, ISRS_E_ARG, m);
     if (!cuts || n_cut < 1) return fail(c, ISRS_E_ARG, "need at least one CUT");
-    for (int q = 0; q < n_cut; ++q) {
-        if (cuts[q] < 0 || cuts[q] >= c->n_ch) return fail(c, ISRS_E_ARG, "CUT index out of range");
-        if (!(c->power[cuts[q]] > 0)) return fail(c, ISRS_E_ARG, "CUT is an inactive channel");
-    }
+    LinkInput L = ctx_link(c, cuts, n_cut);
+    m = validate_link_numerics(L, nu);
+    if (!m.empty()) return fail(c, ISRS_E_ARG, m);
     if (kappa12) {
         for (int t = 0; t < 2 * m_explicit; ++t)
             if (kappa12[t] < 0 || kappa12[t] >= c->n_ch) return fail(c, ISRS_E_ARG, "square index out of range");
     }
-    for (const isrs_span& s : c->spans)
-        if (std::ceil(s.length_km / nu->dz_km) > 1e6) return fail(c, ISRS_E_ARG, "dz too small: more than 1e6 segments");
-
     HIP_TRY(c, hipSetDevice(c->device));
     Plan p;
+    Tuning tu;
     try {
-        build_tables(c, nu, p);
-        build_work(c, nu, cuts, n_cut, kappa12, m_explicit, c->ycap, p);
+        plan_begin(nu, p);
+        plan_link_tables(L, nu, p);
+        plan_link_work(L, 0, nu, kappa12, m_explicit, p);
+        plan_finish(p, c->ycap, tu);
+        plan_queue_shape(c, tu, p);
     } catch (const std::bad_alloc&) {
         return fail(c, ISRS_E_NOMEM, "host allocation failed");
     }
-
-    // upload through pinned staging; wait for the previous call's copies first
-    if (c->ev_upload) HIP_TRY(c, hipEventSynchronize(c->ev_upload));
-    const size_t need = staged(p.spans) + (p.fp32 ? staged(p.seg32) : staged(p.seg64)) + staged(p.Sg) +
-                        staged(p.wt) + staged(p.s3) + staged(p.livep) + staged(p.insts) + staged(p.items) +
-                        staged(p.dlist) + 3 * ((c->n_ch * sizeof(double) + 255) & ~size_t(255));
-    HIP_TRY(c, c->h_stage.ensure(need));
-    char* stage = reinterpret_cast<char*>(c->h_stage.p);
+    Workspace& w = *c->ws;
     int32_t rc;
-    if ((rc = upload(c, c->d_spans, p.spans, stage))) return rc;
-    if (p.fp32) {
-        if ((rc = upload(c, c->d_seg, p.seg32, stage))) return rc;
-    } else {
-        if ((rc = upload(c, c->d_seg, p.seg64, stage))) return rc;
-    }
-    if ((rc = upload(c, c->d_Sg, p.Sg, stage))) return rc;
-    if ((rc = upload(c, c->d_wt, p.wt, stage))) return rc;
-    if ((rc = upload(c, c->d_s3, p.s3, stage))) return rc;
-    if ((rc = upload(c, c->d_livep, p.livep, stage))) return rc;
-    if ((rc = upload(c, c->d_insts, p.insts, stage))) return rc;
-    if ((rc = upload(c, c->d_items, p.items, stage))) return rc;
-    if ((rc = upload(c, c->d_dlist, p.dlist, stage))) return rc;
-    if ((rc = upload(c, c->d_power, c->power, stage))) return rc;
-    if ((rc = upload(c, c->d_phi, c->phi, stage))) return rc;
-    if ((rc = upload(c, c->d_psi, c->psi, stage))) return rc;
-    if (!c->ev_upload) HIP_TRY(c, hipEventCreateWithFlags(&c->ev_upload, hipEventDisableTiming));
-    HIP_TRY(c, hipEventRecord(c->ev_upload, c->stream));
-
-    const size_t n_items = p.items.size();
-    HIP_TRY(c, c->d_partD.ensure(std::max<size_t>(1, n_items) * p.n_groups * 3 * sizeof(double)));
-    HIP_TRY(c, c->d_partE.ensure(std::max<size_t>(1, p.dlist.size()) * 12 * sizeof(double)));
-    size_t max_slots = 0;
-    for (size_t ch = 0; ch + 1 < p.dchunk_begin.size(); ++ch)
-        max_slots = std::max<size_t>(max_slots, p.dchunk_begin[ch + 1] - p.dchunk_begin[ch]);
-    const size_t ybytes = (size_t)p.N * p.N * (p.fp32 ? 8 : 16);
-    HIP_TRY(c, c->d_Y.ensure(std::max<size_t>(1, max_slots) * ybytes));
-
+    if ((rc = plan_upload(c, w, p, c->stream))) return rc;
     auto t1 = std::chrono::steady_clock::now();
-
-    RegionArgs ra{};
-    ra.spans = c->d_spans.as<SpanConst>();
-    ra.seg = c->d_seg.p;
-    ra.Sg = c->d_Sg.as<double>();
-    ra.wt = c->d_wt.as<double>();
-    ra.s3 = c->d_s3.as<double>();
-    ra.livep = c->d_livep.as<int>();
-    ra.insts = c->d_insts.as<InstDesc>();
-    ra.items = c->d_items.as<SquareItem>();
-    ra.partD = c->d_partD.as<double>();
-    ra.ybuf = c->d_Y.p;
-    ra.n_groups = p.n_groups;
-    ra.spb = p.spb;
-    ra.nt = p.nt;
-    ra.N = p.N;
-    ra.n_ch = c->n_ch;
-    ra.n_sp = (int)p.spans.size();
-    ra.gain_mode = c->gain_mode;
-    ra.mu_method = nu->mu_method;
-    ra.h = p.h;
-    ra.spacing = c->spacing;
-
-    EgnArgs ea{};
-    ea.Sg = ra.Sg;
-    ea.wt = ra.wt;
-    ea.s3 = ra.s3;
-    ea.insts = ra.insts;
-    ea.items = ra.items;
-    ea.ybuf = c->d_Y.p;
-    ea.partE = c->d_partE.as<double>();
-    ea.N = p.N;
-    ea.h = p.h;
-
-    const size_t n_chunks = p.chunk_begin.size() - 1;
-    size_t ev_i = 0;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> reg_ev, egn_ev;
-    for (size_t ch = 0; ch < n_chunks; ++ch) {
-        const int b = p.chunk_begin[ch], e = p.chunk_begin[ch + 1];
-        ra.item0 = b;
-        hipEvent_t a0 = nullptr, a1 = nullptr;
-        if (c->profiling) {
-            a0 = pool_event(c, ev_i++);
-            a1 = pool_event(c, ev_i++);
-            if (!a0 || !a1) return fail(c, ISRS_E_DEVICE, "event creation failed");
-            HIP_TRY(c, hipEventRecord(a0, c->stream));
-        }
-        HIP_TRY(c, launch_region(ra, e - b, p.fp32, c->stream));
-        if (c->profiling) {
-            HIP_TRY(c, hipEventRecord(a1, c->stream));
-            reg_ev.push_back({a0, a1});
-        }
-        const int db = p.dchunk_begin[ch], de = p.dchunk_begin[ch + 1];
-        if (de > db) {
-            ea.dlist = c->d_dlist.as<int>() + db;
-            hipEvent_t b0 = nullptr, b1 = nullptr;
-            if (c->profiling) {
-                b0 = pool_event(c, ev_i++);
-                b1 = pool_event(c, ev_i++);
-                if (!b0 || !b1) return fail(c, ISRS_E_DEVICE, "event creation failed");
-                HIP_TRY(c, hipEventRecord(b0, c->stream));
-            }
-            HIP_TRY(c, launch_egn(ea, de - db, p.fp32, c->stream));
-            if (c->profiling) {
-                HIP_TRY(c, hipEventRecord(b1, c->stream));
-                egn_ev.push_back({b0, b1});
-            }
-        }
-    }
-
-    if (!partials_host) {
-        AssembleArgs aa{};
-        aa.insts = ra.insts;
-        aa.items = ra.items;
-        aa.partD = ra.partD;
-        aa.partE = ea.partE;
-        aa.power = c->d_power.as<double>();
-        aa.phi = c->d_phi.as<double>();
-        aa.psi = c->d_psi.as<double>();
-        aa.eta = eta_d;
-        aa.sigma2 = s2_d;
-        aa.terms = terms_d;
-        aa.psd = psd_d;
-        aa.n_groups = p.n_groups;
-        aa.n_f = p.n_f;
-        aa.rs = c->rs;
-        aa.h = p.h;
-        aa.n_cut = n_cut;
-        hipEvent_t c0 = nullptr, c1 = nullptr;
-        if (c->profiling) {
-            c0 = pool_event(c, ev_i++);
-            c1 = pool_event(c, ev_i++);
-            if (!c0 || !c1) return fail(c, ISRS_E_DEVICE, "event creation failed");
-            HIP_TRY(c, hipEventRecord(c0, c->stream));
-        }
-        HIP_TRY(c, launch_assemble(aa, c->stream));
-        if (c->profiling) {
-            HIP_TRY(c, hipEventRecord(c1, c->stream));
-            HIP_TRY(c, hipEventSynchronize(c1));
-            float ms = 0;
-            HIP_TRY(c, hipEventElapsedTime(&ms, c0, c1));
-            c->stats.assemble_ms = ms;
-        }
-    } else {
-        // island partials: D per group summed on the host, coherent sums as computed
-        std::vector<double> pd(n_items * p.n_groups * 3), pe(std::max<size_t>(1, p.dlist.size()) * 12);
-        HIP_TRY(c, hipMemcpyAsync(pd.data(), ra.partD, pd.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-        HIP_TRY(c, hipMemcpyAsync(pe.data(), ea.partE, pe.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    Timings tm;
+    if ((rc = plan_enqueue(c, w, p, tu, c->stream, eta_d, s2_d, terms_d, psd_d, partials_host == nullptr,
+                           c->profiling ? &tm : nullptr)))
+        return rc;
+    if (partials_host) {
+        std::vector<double> pd(p.items.size() * p.n_groups * 3), pe(std::max<size_t>(1, p.dlist.size()) * 12);
+        HIP_TRY(c, hipMemcpyAsync(pd.data(), w.partD.p, pd.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(pe.data(), w.partE.p, pe.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(c, hipStreamSynchronize(c->stream));
-        const double h2 = p.h * p.h;
+        const double h2 = p.links[0].h * p.links[0].h;
         for (int t = 0; t < m_explicit; ++t) {
             const SquareItem& it = p.items[t];
             for (int l = 0; l < 3; ++l) {
@@ -656,47 +854,203 @@ int32_t evaluate(isrs_ctx* c, const isrs_numerics* nu, const int32_t* cuts, int 
                 double* o = partials_host + (size_t)t * 15 + l * 5;
                 const bool valid = (it.lmask >> l) & 1;
                 o[0] = valid ? h2 * D : 0.0;
-                for (int u = 0; u < 4; ++u) o[1 + u] = (valid && it.d_index >= 0) ? pe[(size_t)it.d_index * 12 + l * 4 + u] : 0.0;
+                for (int u = 0; u < 4; ++u)
+                    o[1 + u] = (valid && it.d_index >= 0) ? pe[(size_t)it.d_index * 12 + l * 4 + u] : 0.0;
             }
         }
     }
-
-    auto t2 = std::chrono::steady_clock::now();
-    c->stats.host_prep_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
-    c->stats.region_launches = (int64_t)n_chunks;
-    c->stats.n_squares = (int64_t)n_items;
-    c->stats.n_delta_squares = (int64_t)p.dlist.size();
-    c->stats.n_points_live = p.live_points;
-    c->stats.horner_steps = nu->mu_method == ISRS_MU_SEGMENT ? p.horner_steps : 0;
-    c->stats.alg_flop = p.alg_flop;
-    if (c->profiling) {
-        double rms = 0, ems = 0;
-        for (auto& e : reg_ev) {
-            HIP_TRY(c, hipEventSynchronize(e.second));
-            float ms = 0;
-            HIP_TRY(c, hipEventElapsedTime(&ms, e.first, e.second));
-            rms += ms;
-        }
-        for (auto& e : egn_ev) {
-            HIP_TRY(c, hipEventSynchronize(e.second));
-            float ms = 0;
-            HIP_TRY(c, hipEventElapsedTime(&ms, e.first, e.second));
-            ems += ms;
-        }
-        c->stats.region_ms = rms;
-        c->stats.egn_ms = ems;
-    } else {
-        c->stats.region_ms = c->stats.egn_ms = c->stats.assemble_ms = 0;
-    }
-    (void)t2;
+    record_stats(c, p, std::chrono::duration<double, std::milli>(t1 - t0).count(), c->profiling);
+    if (c->profiling) return collect_timings(c, tm);
     return ISRS_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Batches
+// ---------------------------------------------------------------------------
+struct isrs_batch {
+    isrs_ctx* ctx = nullptr;
+    int n_links = 0;
+    std::vector<int> ch_off, span_off, cut_off;
+    std::vector<int32_t> cuts;
+    std::vector<double> spacing, rs, rolloff;
+    std::vector<int> gain;
+    std::vector<double> power, phi, psi;
+    std::vector<isrs_span> spans;
+    int64_t n_cuts = 0;
+
+    Workspace ws;
+    Plan plan;
+    bool planned = false;
+    isrs_numerics key{};
+    Tuning tuning;
+    bool warm = false;      // the current plan has run once outside a capture
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    DevBuf out;
+
+    void drop_graph()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+    }
+    LinkInput link(int l) const
+    {
+        LinkInput L;
+        L.n_ch = ch_off[l + 1] - ch_off[l];
+        L.spacing = spacing[l];
+        L.rs = rs[l];
+        L.rolloff = rolloff[l];
+        L.power = power.data() + ch_off[l];
+        L.phi = phi.data() + ch_off[l];
+        L.psi = psi.data() + ch_off[l];
+        L.spans = spans.data() + span_off[l];
+        L.n_sp = span_off[l + 1] - span_off[l];
+        L.gain_mode = gain[l];
+        L.cuts = cuts.data() + cut_off[l];
+        L.n_cut = cut_off[l + 1] - cut_off[l];
+        return L;
+    }
+};
+
+namespace {
+
+bool same_numerics(const isrs_numerics& a, const isrs_numerics& b)
+{
+    return a.dz_km == b.dz_km && a.n1 == b.n1 && a.n2 == b.n2 && a.n_f == b.n_f && a.egn == b.egn &&
+           a.precision == b.precision && a.mu_method == b.mu_method;
+}
+
+int32_t batch_plan(isrs_ctx* c, isrs_batch* b, const isrs_numerics* nu)
+{
+    std::string m = validate_numerics_msg(nu);
+    if (!m.empty()) return fail(c, ISRS_E_ARG, m);
+    for (int l = 0; l < b->n_links; ++l) {
+        m = validate_link_numerics(b->link(l), nu);
+        if (!m.empty()) return fail(c, ISRS_E_ARG, "link " + std::to_string(l) + ": " + m);
+    }
+    b->drop_graph();
+    b->planned = false;
+    Plan p;
+    try {
+        plan_begin(nu, p);
+        for (int l = 0; l < b->n_links; ++l) plan_link_tables(b->link(l), nu, p);
+        for (int l = 0; l < b->n_links; ++l) plan_link_work(b->link(l), l, nu, nullptr, 0, p);
+        plan_finish(p, c->ycap, b->tuning);
+        plan_queue_shape(c, b->tuning, p);
+    } catch (const std::bad_alloc&) {
+        return fail(c, ISRS_E_NOMEM, "host allocation failed");
+    }
+    HIP_TRY(c, hipSetDevice(c->device));
+    int32_t rc = plan_upload(c, b->ws, p, c->stream);
+    if (rc) return rc;
+    HIP_TRY(c, b->out.ensure(std::max<int64_t>(1, b->n_cuts) * sizeof(double)));
+    b->plan = std::move(p);
+    b->key = *nu;
+    b->planned = true;
+    b->warm = false;
+    return ISRS_OK;
+}
+
+// Runs a planned batch into eta_d.  A new plan runs eagerly once (every
+// kernel is loaded and launched outside a capture); later calls capture the
+// launches into a graph once and replay it.
+int32_t batch_run(isrs_ctx* c, isrs_batch* b, double* eta_d, bool use_graph)
+{
+    if (c->profiling || !use_graph || !b->warm) {
+        b->warm = true;
+        Timings tm;
+        int32_t rc = plan_enqueue(c, b->ws, b->plan, b->tuning, c->stream, eta_d, nullptr, nullptr, nullptr, true,
+                                  c->profiling ? &tm : nullptr);
+        if (rc) return rc;
+        record_stats(c, b->plan, 0.0, c->profiling);
+        if (c->profiling) return collect_timings(c, tm);
+        return ISRS_OK;
+    }
+    if (!b->exec) {
+        HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        int32_t rc = plan_enqueue(c, b->ws, b->plan, b->tuning, c->stream, b->out.as<double>(), nullptr, nullptr,
+                                  nullptr, true, nullptr);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(c->stream, &g);
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
+        b->graph = g;
+        HIP_TRY(c, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    }
+    HIP_TRY(c, hipGraphLaunch(b->exec, c->stream));
+    if (eta_d != b->out.as<double>())
+        HIP_TRY(c, hipMemcpyAsync(eta_d, b->out.p, b->n_cuts * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    record_stats(c, b->plan, 0.0, false);
+    return ISRS_OK;
+}
+
+std::string tune_key(const isrs_batch* b, const isrs_numerics* nu, const char* arch)
+{
+    int kmax = 0, smax = 0;
+    for (int l = 0; l < b->n_links; ++l) {
+        const LinkInput L = b->link(l);
+        smax = std::max(smax, L.n_sp);
+        for (int s = 0; s < L.n_sp; ++s) kmax = std::max(kmax, (int)std::ceil(L.spans[s].length_km / nu->dz_km));
+    }
+    std::ostringstream os;
+    os << arch << "|N" << nu->n1 << "|K" << ((kmax + 31) / 32) * 32 << "|S" << ((smax + 7) / 8) * 8 << "|P"
+       << nu->precision << "|M" << nu->mu_method << "|F" << nu->n_f;
+    return os.str();
+}
+
+// Minimal line-oriented cache: one `key mode bpc sort spb ms` record per line.
+std::map<std::string, std::vector<double>> read_cache(const char* path)
+{
+    std::map<std::string, std::vector<double>> out;
+    if (!path) return out;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        // {"key": "...", "mode": m, "blocks_per_cu": b, "sort": s, "strips": p, "ms": t}
+        auto kpos = line.find("\"key\": \"");
+        if (kpos == std::string::npos) continue;
+        auto kend = line.find('"', kpos + 8);
+        std::string key = line.substr(kpos + 8, kend - kpos - 8);
+        std::vector<double> v;
+        for (const char* name : {"\"mode\": ", "\"blocks_per_cu\": ", "\"sort\": ", "\"strips\": ", "\"ms\": "}) {
+            auto p = line.find(name);
+            if (p == std::string::npos) break;
+            v.push_back(std::atof(line.c_str() + p + std::strlen(name)));
+        }
+        if (v.size() == 5) out[key] = v;
+    }
+    return out;
+}
+
+bool write_cache(const char* path, const std::map<std::string, std::vector<double>>& m)
+{
+    if (!path) return true;
+    std::ofstream f(path, std::ios::trunc);
+    if (!f) return false;
+    f << "[\n";
+    size_t i = 0;
+    for (auto& kv : m) {
+        f << "{\"key\": \"" << kv.first << "\", \"mode\": " << (int)kv.second[0]
+          << ", \"blocks_per_cu\": " << (int)kv.second[1] << ", \"sort\": " << (int)kv.second[2]
+          << ", \"strips\": " << (int)kv.second[3] << ", \"ms\": " << kv.second[4] << "}"
+          << (++i < m.size() ? ",\n" : "\n");
+    }
+    f << "]\n";
+    return (bool)f;
 }
 
 }  // namespace
 
 extern "C" {
 
-const char* isrs_version(void) { return "isrs-egn 0.1 (gfx950)"; }
+const char* isrs_version(void) { return "isrs-egn 0.2 (gfx950)"; }
 
 int32_t isrs_validate_spectrum(const isrs_spectrum* s)
 {
@@ -743,12 +1097,18 @@ int32_t isrs_create(isrs_ctx** out, int32_t device, void* hip_stream)
         return ISRS_E_DEVICE;
     }
     isrs_ctx* c = new (std::nothrow) isrs_ctx();
-    if (!c) {
+    Workspace* w = new (std::nothrow) Workspace();
+    if (!c || !w) {
+        delete c;
+        delete w;
         g_create_error = "host allocation failed";
         return ISRS_E_NOMEM;
     }
+    c->ws = w;
     c->device = device;
+    c->n_cu = prop.multiProcessorCount;
     if (hipSetDevice(device) != hipSuccess) {
+        delete w;
         delete c;
         g_create_error = "hipSetDevice failed";
         return ISRS_E_DEVICE;
@@ -757,6 +1117,7 @@ int32_t isrs_create(isrs_ctx** out, int32_t device, void* hip_stream)
         c->stream = reinterpret_cast<hipStream_t>(hip_stream);
     } else {
         if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete w;
             delete c;
             g_create_error = "stream creation failed";
             return ISRS_E_DEVICE;
@@ -772,12 +1133,8 @@ int32_t isrs_destroy(isrs_ctx* c)
     if (!c) return ISRS_E_ARG;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
-    DevBuf* bufs[] = {&c->d_spans, &c->d_seg, &c->d_Sg, &c->d_wt, &c->d_s3, &c->d_livep, &c->d_insts, &c->d_items,
-                      &c->d_partD, &c->d_partE, &c->d_Y, &c->d_dlist, &c->d_out, &c->d_power, &c->d_phi, &c->d_psi};
-    for (DevBuf* b : bufs) b->release();
-    c->h_stage.release();
-    if (c->ev_upload) (void)hipEventDestroy(c->ev_upload);
-    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    c->ws->release();
+    delete c->ws;
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
     return ISRS_OK;
@@ -859,8 +1216,8 @@ int32_t isrs_eval_eta(isrs_ctx* c, const isrs_numerics* nu, const int32_t* cuts,
     if (n_cut < 1) return fail(c, ISRS_E_ARG, "need at least one CUT");
     HIP_TRY(c, hipSetDevice(c->device));
     const size_t n = (size_t)n_cut;
-    HIP_TRY(c, c->d_out.ensure(n * 7 * sizeof(double)));
-    double* d = c->d_out.as<double>();
+    HIP_TRY(c, c->ws->out.ensure(n * 7 * sizeof(double)));
+    double* d = c->ws->out.as<double>();
     int32_t rc = evaluate(c, nu, cuts, n_cut, nullptr, 0, d, d + n, d + 2 * n, nullptr, nullptr);
     if (rc) return rc;
     std::vector<double> h(n * 7);
@@ -886,8 +1243,8 @@ int32_t isrs_eval_psd(isrs_ctx* c, const isrs_numerics* nu, const int32_t* cuts,
     if (n_cut < 1) return fail(c, ISRS_E_ARG, "need at least one CUT");
     HIP_TRY(c, hipSetDevice(c->device));
     const size_t n = (size_t)n_cut, nf = (size_t)nu->n_f;
-    HIP_TRY(c, c->d_out.ensure(n * (1 + nf) * sizeof(double)));
-    double* d = c->d_out.as<double>();
+    HIP_TRY(c, c->ws->out.ensure(n * (1 + nf) * sizeof(double)));
+    double* d = c->ws->out.as<double>();
     int32_t rc = evaluate(c, nu, cuts, n_cut, nullptr, 0, d, nullptr, nullptr, d + n, nullptr);
     if (rc) return rc;
     std::vector<double> h(n * nf);
@@ -913,6 +1270,214 @@ int32_t isrs_eval_islands(isrs_ctx* c, const isrs_numerics* nu, int32_t cut, con
     if (rc) return rc;
     for (size_t t = 0; t < (size_t)m * 15; ++t)
         if (!is_fin(partials[t])) return fail(c, ISRS_E_NUMERIC, "non-finite island partial");
+    return ISRS_OK;
+}
+
+int32_t isrs_batch_create(isrs_ctx* c, const isrs_link_batch* in, isrs_batch** out)
+{
+    if (!c) return ISRS_E_ARG;
+    if (!in || !out) return fail(c, ISRS_E_ARG, "batch or output is null");
+    *out = nullptr;
+    if (in->n_links < 1 || !in->ch_offset || !in->span_offset || !in->spacing_thz || !in->symbol_rate_thz ||
+        !in->rolloff || !in->power_w || !in->phi || !in->psi || !in->spans)
+        return fail(c, ISRS_E_ARG, "batch arrays must not be null and n_links >= 1");
+    if ((in->cut_offset == nullptr) != (in->cuts == nullptr))
+        return fail(c, ISRS_E_ARG, "cut_offset and cuts must both be set or both be null");
+    isrs_batch* b = new (std::nothrow) isrs_batch();
+    if (!b) return fail(c, ISRS_E_NOMEM, "host allocation failed");
+    b->ctx = c;
+    b->n_links = in->n_links;
+    const int nl = in->n_links;
+    b->cut_off.push_back(0);
+    for (int l = 0; l < nl; ++l) {
+        const int c0 = in->ch_offset[l], c1 = in->ch_offset[l + 1];
+        const int s0 = in->span_offset[l], s1 = in->span_offset[l + 1];
+        const std::string where = "link " + std::to_string(l) + ": ";
+        if (c0 < 0 || c1 <= c0 || s0 < 0 || s1 <= s0 || (l > 0 && (c0 != in->ch_offset[l] || s0 != in->span_offset[l]))) {
+            delete b;
+            return fail(c, ISRS_E_ARG, where + "bad channel or span offsets");
+        }
+        std::string m = validate_spectrum_fields(c1 - c0, in->spacing_thz[l], in->symbol_rate_thz[l],
+                                                 in->rolloff[l], in->power_w + c0, in->phi + c0, in->psi + c0);
+        if (!m.empty()) {
+            delete b;
+            return fail(c, ISRS_E_SPECTRUM, where + m);
+        }
+        const int gm = in->gain_mode ? in->gain_mode[l] : ISRS_GAIN_EQUALIZED;
+        m = validate_link_msg(in->spans + s0, s1 - s0, gm);
+        if (!m.empty()) {
+            delete b;
+            return fail(c, ISRS_E_LINK, where + m);
+        }
+        if (in->cuts) {
+            const int q0 = in->cut_offset[l], q1 = in->cut_offset[l + 1];
+            if (q0 < 0 || q1 < q0 || q0 != b->cut_off.back()) {
+                delete b;
+                return fail(c, ISRS_E_ARG, where + "bad cut offsets");
+            }
+            for (int q = q0; q < q1; ++q) {
+                const int k = in->cuts[q];
+                if (k < 0 || k >= c1 - c0 || !(in->power_w[c0 + k] > 0)) {
+                    delete b;
+                    return fail(c, ISRS_E_ARG, where + "CUT out of range or inactive");
+                }
+                b->cuts.push_back(k);
+            }
+        } else {
+            for (int k = 0; k < c1 - c0; ++k)
+                if (in->power_w[c0 + k] > 0) b->cuts.push_back(k);
+        }
+        b->cut_off.push_back((int)b->cuts.size());
+        b->spacing.push_back(in->spacing_thz[l]);
+        b->rs.push_back(in->symbol_rate_thz[l]);
+        b->rolloff.push_back(in->rolloff[l]);
+        b->gain.push_back(gm);
+    }
+    const int nch = in->ch_offset[nl], nsp = in->span_offset[nl];
+    b->ch_off.assign(in->ch_offset, in->ch_offset + nl + 1);
+    b->span_off.assign(in->span_offset, in->span_offset + nl + 1);
+    b->power.assign(in->power_w, in->power_w + nch);
+    b->phi.assign(in->phi, in->phi + nch);
+    b->psi.assign(in->psi, in->psi + nch);
+    b->spans.assign(in->spans, in->spans + nsp);
+    b->n_cuts = (int64_t)b->cuts.size();
+    b->tuning.mode = 1;  // queue by default for batches
+    *out = b;
+    return ISRS_OK;
+}
+
+int32_t isrs_batch_destroy(isrs_batch* b)
+{
+    if (!b) return ISRS_E_ARG;
+    if (b->ctx) {
+        (void)hipSetDevice(b->ctx->device);
+        (void)hipStreamSynchronize(b->ctx->stream);
+    }
+    b->drop_graph();
+    b->ws.release();
+    b->out.release();
+    delete b;
+    return ISRS_OK;
+}
+
+int32_t isrs_batch_num_cuts(const isrs_batch* b, int64_t* n)
+{
+    if (!b || !n) return ISRS_E_ARG;
+    *n = b->n_cuts;
+    return ISRS_OK;
+}
+
+int32_t isrs_batch_eval_dev(isrs_ctx* c, isrs_batch* b, const isrs_numerics* nu, double* eta_dev)
+{
+    if (!c) return ISRS_E_ARG;
+    if (!b || !eta_dev) return fail(c, ISRS_E_ARG, "batch or output is null");
+    if (b->ctx != c) return fail(c, ISRS_E_ARG, "batch belongs to another context");
+    std::string m = validate_numerics_msg(nu);
+    if (!m.empty()) return fail(c, ISRS_E_ARG, m);
+    HIP_TRY(c, hipSetDevice(c->device));
+    auto t0 = std::chrono::steady_clock::now();
+    if (!b->planned || !same_numerics(b->key, *nu)) {
+        int32_t rc = batch_plan(c, b, nu);
+        if (rc) return rc;
+    }
+    auto t1 = std::chrono::steady_clock::now();
+    int32_t rc = batch_run(c, b, eta_dev, true);
+    c->stats.host_prep_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    return rc;
+}
+
+int32_t isrs_batch_eval(isrs_ctx* c, isrs_batch* b, const isrs_numerics* nu, double* eta)
+{
+    if (!c) return ISRS_E_ARG;
+    if (!b || !eta) return fail(c, ISRS_E_ARG, "batch or output is null");
+    if (b->ctx != c) return fail(c, ISRS_E_ARG, "batch belongs to another context");
+    std::string m = validate_numerics_msg(nu);
+    if (!m.empty()) return fail(c, ISRS_E_ARG, m);
+    HIP_TRY(c, hipSetDevice(c->device));
+    if (!b->planned || !same_numerics(b->key, *nu)) {
+        int32_t rc = batch_plan(c, b, nu);
+        if (rc) return rc;
+    }
+    int32_t rc = batch_run(c, b, b->out.as<double>(), true);
+    if (rc) return rc;
+    std::vector<double> h(b->n_cuts);
+    HIP_TRY(c, hipMemcpyAsync(h.data(), b->out.p, b->n_cuts * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (int64_t q = 0; q < b->n_cuts; ++q) {
+        if (!is_fin(h[q])) return fail(c, ISRS_E_NUMERIC, "non-finite NLI result");
+        eta[q] = h[q];
+    }
+    return ISRS_OK;
+}
+
+int32_t isrs_batch_get_tuning(const isrs_batch* b, int32_t* mode, int32_t* bpc, int32_t* sort, int32_t* strips)
+{
+    if (!b) return ISRS_E_ARG;
+    if (mode) *mode = b->tuning.mode;
+    if (bpc) *bpc = b->tuning.blocks_per_cu;
+    if (sort) *sort = b->tuning.sort;
+    if (strips) *strips = b->planned ? b->plan.spb : b->tuning.spb;
+    return ISRS_OK;
+}
+
+int32_t isrs_autotune(isrs_ctx* c, isrs_batch* b, const isrs_numerics* nu, const char* cache_path)
+{
+    if (!c) return ISRS_E_ARG;
+    if (!b) return fail(c, ISRS_E_ARG, "batch is null");
+    if (b->ctx != c) return fail(c, ISRS_E_ARG, "batch belongs to another context");
+    std::string m = validate_numerics_msg(nu);
+    if (!m.empty()) return fail(c, ISRS_E_ARG, m);
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipDeviceProp_t prop;
+    HIP_TRY(c, hipGetDeviceProperties(&prop, c->device));
+    char arch[64];
+    std::snprintf(arch, sizeof arch, "%.20s-%dcu", prop.gcnArchName, prop.multiProcessorCount);
+    const std::string key = tune_key(b, nu, arch);
+    auto cache = read_cache(cache_path);
+    auto hit = cache.find(key);
+    if (hit != cache.end()) {
+        b->tuning = {(int)hit->second[0], (int)hit->second[1], (int)hit->second[2], (int)hit->second[3]};
+        b->planned = false;
+        b->drop_graph();
+        return batch_plan(c, b, nu);
+    }
+    // candidates: grid mode at two strip groupings, queue mode with 1..3
+    // blocks per CU, sorted and natural order
+    const int nt = (nu->n1 + TILE - 1) / TILE;
+    std::vector<Tuning> cands;
+    for (int spb : {1, nt}) {
+        cands.push_back({0, 0, 0, spb});
+        for (int bpc : {1, 2, 3})
+            for (int sort : {1, 0}) cands.push_back({1, bpc, sort, spb});
+        if (nt == 1) break;
+    }
+    const bool prof = c->profiling;
+    c->profiling = true;
+    double best = 1e300;
+    Tuning best_t = b->tuning;
+    for (const Tuning& t : cands) {
+        b->tuning = t;
+        b->planned = false;
+        int32_t rc = batch_plan(c, b, nu);
+        if (!rc) rc = batch_run(c, b, b->out.as<double>(), false);  // warm
+        if (!rc) rc = batch_run(c, b, b->out.as<double>(), false);
+        if (rc) {
+            c->profiling = prof;
+            return rc;
+        }
+        const double ms = c->stats.region_ms + c->stats.egn_ms;
+        if (ms < best) {
+            best = ms;
+            best_t = t;
+        }
+    }
+    c->profiling = prof;
+    b->tuning = best_t;
+    b->planned = false;
+    int32_t rc = batch_plan(c, b, nu);
+    if (rc) return rc;
+    cache[key] = {(double)best_t.mode, (double)best_t.blocks_per_cu, (double)best_t.sort, (double)b->plan.spb, best};
+    if (!write_cache(cache_path, cache)) return fail(c, ISRS_E_ARG, "cannot write the autotune cache file");
     return ISRS_OK;
 }
 

@@ -9,7 +9,7 @@
 namespace isrs {
 
 // Region tile: TILE x TILE grid points per pass, 256 threads, each thread
-// owns 4 points of one tile column (rows r0, r0+8, r0+16, r0+24).
+// owns 4 points of one tile column.
 constexpr int TILE = 32;
 constexpr int THREADS = 256;
 constexpr int PPT = 4;                // points per thread per tile
@@ -46,10 +46,23 @@ struct SegRow32 {
     float A, zeta, ratio, pad;
 };
 
-// One (CUT, outer-frequency) instance.
+// One link (spectrum + spans) of an evaluation; offsets index the
+// concatenated tables of all links.
+struct LinkDesc {
+    int span0, n_sp;      // spans[span0 .. span0 + n_sp)
+    int n_ch, gain_mode;
+    int ch0;              // power / phi / psi
+    int tab0;             // island weight / S(f3) tables: n_f * 3 * (2N-1) per link
+    int livep0;           // live prefix counts: n_f * 3 * 2N per link
+    int sg0;              // S at the grid points: N per link
+    double spacing, h, rs;
+};
+
+// One (link, CUT, outer-frequency) instance.
 struct InstDesc {
     double f;        // outer frequency offset from the CUT centre, THz
-    int cut;         // channel index
+    int link;
+    int cut;         // channel index within the link
     int nf_idx;      // outer-frequency sample -> island tables
     int sq_begin;    // its squares in the work list
     int sq_end;
@@ -66,31 +79,35 @@ struct SquareItem {
     float mult;      // 2 for k1 < k2 (mirror square folded in), else 1
 };
 
+// A launch covers work units [unit0, unit0 + n_units); unit u is strip group
+// u % n_groups of square u / n_groups.  With a queue, blocks pop positions
+// from *counter and run unit order[unit0 + pos] (a cost-sorted permutation of
+// the launch's units); without one, block b runs unit unit0 + b.
 struct RegionArgs {
+    const LinkDesc* links;
     const SpanConst* spans;
     const void* seg;          // SegRow32 or SegRow64 rows
-    const double* Sg;         // [N] S(f) at the grid points
-    const double* wt;         // [n_f][3][2N-1] island weight per anti-diagonal (1, 1/2 on a tie, 0)
-    const double* s3;         // [n_f][3][2N-1] S(f3) per anti-diagonal
-    const int* livep;         // [n_f][3][2N] prefix counts of live anti-diagonals
+    const double* Sg;
+    const double* wt;
+    const double* s3;
+    const int* livep;
     const InstDesc* insts;
     const SquareItem* items;
-    double* partD;            // [n_items][n_groups][3]
+    double* partD;            // [units][3]
     void* ybuf;               // Upsilon of the chunk's coherent-sum squares, [slot][N][N] complex
-    int item0;                // first item of this chunk
+    const int* order;         // queue mode: permutation of units, else null
+    int* counter;             // queue mode: head counter (zeroed before the launch)
+    int unit0;
+    int n_units;
     int n_groups;             // strip groups per square
     int spb;                  // tile strips per group
     int nt;                   // tiles per side
     int N;
-    int n_ch;
-    int n_sp;
-    int gain_mode;
     int mu_method;
-    double h;                 // grid step, THz
-    double spacing;           // channel spacing, THz
 };
 
 struct EgnArgs {
+    const LinkDesc* links;
     const double* Sg;
     const double* wt;
     const double* s3;
@@ -100,15 +117,15 @@ struct EgnArgs {
     const void* ybuf;
     double* partE;            // [n_delta][3][4]
     int N;
-    double h;
 };
 
 struct AssembleArgs {
+    const LinkDesc* links;
     const InstDesc* insts;
     const SquareItem* items;
     const double* partD;
     const double* partE;
-    const double* power;      // [n_ch]
+    const double* power;      // concatenated per link
     const double* phi;
     const double* psi;
     double* eta;              // [n_cut]
@@ -117,14 +134,15 @@ struct AssembleArgs {
     double* psd;              // [n_cut][n_f] or null
     int n_groups;
     int n_f;
-    double rs;
-    double h;
     int n_cut;
 };
 
-// Kernel launchers (isrs_kernels.hip).
-hipError_t launch_region(const RegionArgs& a, int n_items, bool fp32, hipStream_t st);
+// Kernel launchers (isrs_kernels.hip).  blocks = 0 launches one block per
+// unit; blocks > 0 launches that many persistent blocks on the queue.
+hipError_t launch_region(const RegionArgs& a, int blocks, bool fp32, hipStream_t st);
+hipError_t launch_zero_counter(int* counter, hipStream_t st);
 hipError_t launch_egn(const EgnArgs& a, int n_delta, bool fp32, hipStream_t st);
 hipError_t launch_assemble(const AssembleArgs& a, hipStream_t st);
+int region_blocks_per_cu(bool fp32, int mu_method);
 
 }  // namespace isrs

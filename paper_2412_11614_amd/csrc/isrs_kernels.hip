@@ -84,8 +84,12 @@ __device__ double block_sum(double v, double* sh)
 }
 
 
+template <typename R>
+using VecOf = typename Prec<R>::Vec;
+
+// One work unit: strip group u % n_groups of square u / n_groups.
 template <typename R, int MU>
-__global__ void __launch_bounds__(THREADS) region_kernel(RegionArgs a)
+__device__ void region_unit(const RegionArgs& a, const int u, VecOf<R>* g_vec, double* red)
 {
     using P = Prec<R>;
     using V2 = typename P::V2;
@@ -93,18 +97,17 @@ __global__ void __launch_bounds__(THREADS) region_kernel(RegionArgs a)
     using Seg = typename P::Seg;
     constexpr int KC = P::KC, KP = P::KP, VW = P::VW, KPV = KP / VW;
     // g rows of the tile's anti-diagonals; read as 16-byte vectors, written as scalars
-    __shared__ Vec g_vec[NAD * KPV];
-    __shared__ double red[THREADS / 64];
     R* const g_lds = reinterpret_cast<R*>(g_vec);
 
     const int tid = threadIdx.x;
-    const int item = a.item0 + blockIdx.x / a.n_groups;
-    const int grp = blockIdx.x % a.n_groups;
+    const int item = u / a.n_groups;
+    const int grp = u % a.n_groups;
     const SquareItem it = a.items[item];
     const InstDesc in = a.insts[it.inst];
+    const LinkDesc lk = a.links[in.link];
     const int N = a.N, AD = 2 * N - 1;
-    const double h = a.h, df = a.spacing;
-    const double half_grid = 0.5 * (a.n_ch - 1);
+    const double h = lk.h, df = lk.spacing;
+    const double half_grid = 0.5 * (lk.n_ch - 1);
     // absolute offsets of the square (THz): d1 = d1b + f1, d2 = d2b + f2,
     // a + b = sb + f1 + f2, a + b - c = x3b + f1 + f2, c = cabs
     const double d1b = (it.k1 - in.cut) * df - in.f;
@@ -112,9 +115,11 @@ __global__ void __launch_bounds__(THREADS) region_kernel(RegionArgs a)
     const double sb = (it.k1 + it.k2 - 2.0 * half_grid) * df;
     const double x3b = (it.k1 + it.k2 - in.cut - half_grid) * df - in.f;
     const double cabs = (in.cut - half_grid) * df + in.f;
-    const double* wt = a.wt + (size_t)in.nf_idx * 3 * AD;
-    const double* s3 = a.s3 + (size_t)in.nf_idx * 3 * AD;
-    const int* livep = a.livep + (size_t)in.nf_idx * 3 * (AD + 1);
+    const double* wt = a.wt + lk.tab0 + (size_t)in.nf_idx * 3 * AD;
+    const double* s3 = a.s3 + lk.tab0 + (size_t)in.nf_idx * 3 * AD;
+    const int* livep = a.livep + lk.livep0 + (size_t)in.nf_idx * 3 * (AD + 1);
+    const double* Sg = a.Sg + lk.sg0;
+    const SpanConst* spans = a.spans + lk.span0;
     const Seg* seg = reinterpret_cast<const Seg*>(a.seg);
     V2* ybuf = it.y_slot >= 0 ? reinterpret_cast<V2*>(a.ybuf) + (size_t)it.y_slot * N * N : nullptr;
 
@@ -163,8 +168,8 @@ __global__ void __launch_bounds__(THREADS) region_kernel(RegionArgs a)
                 ui[r] = R(0);
             }
 
-            for (int s = 0; s < a.n_sp; ++s) {
-                const SpanConst sc = a.spans[s];
+            for (int s = 0; s < lk.n_sp; ++s) {
+                const SpanConst sc = spans[s];
                 R qr[PPT], qi[PPT], i0r[PPT], i0i[PPT], rr[PPT], ri[PPT];
 #pragma unroll
                 for (int r = 0; r < PPT; ++r) {
@@ -174,7 +179,7 @@ __global__ void __launch_bounds__(THREADS) region_kernel(RegionArgs a)
                     R st, ct;
                     sincos_rev(R(tt), &st, &ct);
                     R gm = R(sc.gamma);
-                    if (a.gain_mode == 1) gm *= exp_r(R(sc.pi_a - sc.pi_s * sab[r] + sc.pi_c * cabs));
+                    if (lk.gain_mode == 1) gm *= exp_r(R(sc.pi_a - sc.pi_s * sab[r] + sc.pi_c * cabs));
                     rr[r] = gm * ct;
                     ri[r] = gm * st;
                     const double chi = d12[r] * (sc.c2x + sc.c3x * sab[r]);
@@ -284,13 +289,13 @@ __global__ void __launch_bounds__(THREADS) region_kernel(RegionArgs a)
             }
 
             // GN island sums (Eq. 17) and the coherent-sum buffer
-            const double S1 = ip < N ? a.Sg[ip] : 0.0;
+            const double S1 = ip < N ? Sg[ip] : 0.0;
 #pragma unroll
             for (int r = 0; r < PPT; ++r) {
                 if (!ok[r]) continue;
                 const int jr = j0 + lj + 8 * r;
                 const int m = mb + mm[r];
-                const double S2 = a.Sg[jr];
+                const double S2 = Sg[jr];
                 const double u2 = (double)ur[r] * (double)ur[r] + (double)ui[r] * (double)ui[r];
                 const double v = S1 * S1 * S2 * S2 * u2;
 #pragma unroll
@@ -303,12 +308,51 @@ __global__ void __launch_bounds__(THREADS) region_kernel(RegionArgs a)
             }
         }
     }
-    double* out = a.partD + ((size_t)item * a.n_groups + grp) * 3;
+    double* out = a.partD + (size_t)u * 3;
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
         const double v = block_sum(dacc[l], red);
         if (tid == 0) out[l] = v;
     }
+}
+
+// FP32: at most 168 VGPRs, three waves per SIMD
+template <typename R>
+constexpr int region_min_waves() { return sizeof(R) == 4 ? 3 : 2; }
+
+template <typename R, int MU>
+__global__ void __launch_bounds__(THREADS, region_min_waves<R>()) region_kernel(RegionArgs a)
+{
+    __shared__ VecOf<R> g_vec[NAD * (Prec<R>::KP / Prec<R>::VW)];
+    __shared__ double red[THREADS / 64];
+    region_unit<R, MU>(a, a.unit0 + blockIdx.x, g_vec, red);
+}
+
+// Persistent blocks on a queue: every block pops unit positions until the
+// launch's units are exhausted, so every block reaches the exit.
+template <typename R, int MU>
+__global__ void __launch_bounds__(THREADS, region_min_waves<R>()) region_queue_kernel(RegionArgs a)
+{
+    __shared__ VecOf<R> g_vec[NAD * (Prec<R>::KP / Prec<R>::VW)];
+    __shared__ double red[THREADS / 64];
+    __shared__ int pos_s;
+    // a block can take at most n_units positions, so the loop is bounded even
+    // if the counter were not reset
+    for (int iter = 0; iter <= a.n_units; ++iter) {
+        if (threadIdx.x == 0) pos_s = atomicAdd(a.counter, 1);
+        __syncthreads();
+        const int pos = pos_s;
+        __syncthreads();
+        if (pos < 0 || pos >= a.n_units) break;
+        region_unit<R, MU>(a, a.order[a.unit0 + pos], g_vec, red);
+    }
+}
+
+// Resets a queue head with an atomic, so the reset is made where the queue's
+// atomics are performed.
+__global__ void zero_counter_kernel(int* c)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) atomicExch(c, 0);
 }
 
 // Coherent sums of one square for the format terms (bare, grid weights included):
@@ -325,12 +369,13 @@ __global__ void __launch_bounds__(THREADS) egn_kernel(EgnArgs a)
     const int item = a.dlist[blockIdx.x];
     const SquareItem it = a.items[item];
     const InstDesc in = a.insts[it.inst];
+    const LinkDesc lk = a.links[in.link];
     const int N = a.N, AD = 2 * N - 1;
-    const double h = a.h;
-    const double* wt = a.wt + (size_t)in.nf_idx * 3 * AD;
-    const double* s3 = a.s3 + (size_t)in.nf_idx * 3 * AD;
+    const double h = lk.h;
+    const double* wt = a.wt + lk.tab0 + (size_t)in.nf_idx * 3 * AD;
+    const double* s3 = a.s3 + lk.tab0 + (size_t)in.nf_idx * 3 * AD;
     const V2* Y = reinterpret_cast<const V2*>(a.ybuf) + (size_t)it.y_slot * N * N;
-    const double* Sg = a.Sg;
+    const double* Sg = a.Sg + lk.sg0;
     const int em = it.egn_mask;
     double res[3][4];
 #pragma unroll
@@ -447,9 +492,13 @@ __global__ void __launch_bounds__(THREADS) assemble_kernel(AssembleArgs a)
 {
     __shared__ double red[THREADS / 64];
     const int q = blockIdx.x, tid = threadIdx.x;
-    const double R = a.rs, R2 = R * R, R3 = R2 * R;
     const double cD = 16.0 / 27.0, cE = 16.0 / 27.0, cF = 32.0 / 81.0, cG = 16.0 / 81.0, cH = 16.0 / 81.0;
-    const double h2 = a.h * a.h;
+    const LinkDesc lk = a.links[a.insts[q * a.n_f].link];
+    const double R = lk.rs, R2 = R * R, R3 = R2 * R;
+    const double h2 = lk.h * lk.h;
+    const double* power = a.power + lk.ch0;
+    const double* phi = a.phi + lk.ch0;
+    const double* psi = a.psi + lk.ch0;
     double s2 = 0.0, tot[5] = {0, 0, 0, 0, 0};
     int cut = 0;
     for (int n = 0; n < a.n_f; ++n) {
@@ -464,7 +513,7 @@ __global__ void __launch_bounds__(THREADS) assemble_kernel(AssembleArgs a)
             for (int l = 0; l < 3; ++l) {
                 if (!((it.lmask >> l) & 1)) continue;
                 const int k3 = it.k1 + it.k2 - in.cut + (l - 1);
-                const double P = a.power[it.k1] * a.power[it.k2] * a.power[k3];
+                const double P = power[it.k1] * power[it.k2] * power[k3];
                 double D = 0.0;
                 for (int g = 0; g < a.n_groups; ++g) D += pd[g * 3 + l];
                 t[0] += P * it.mult * cD * R3 * h2 * D;
@@ -474,18 +523,18 @@ __global__ void __launch_bounds__(THREADS) assemble_kernel(AssembleArgs a)
                     // the mirror square (k2, k1) has F = this square's E when k3 == k1
                     // and E = this square's F when k3 == k2 (f1 <-> f2 symmetry)
                     if (k3 == it.k1) {
-                        t[1] += P * a.phi[it.k1] * cE * R2 * e[0];
-                        t[2] += P * a.phi[it.k1] * cF * R2 * e[0];
+                        t[1] += P * phi[it.k1] * cE * R2 * e[0];
+                        t[2] += P * phi[it.k1] * cF * R2 * e[0];
                     }
                     if (k3 == it.k2) {
-                        t[2] += P * a.phi[it.k2] * cF * R2 * e[1];
-                        t[1] += P * a.phi[it.k2] * cE * R2 * e[1];
+                        t[2] += P * phi[it.k2] * cF * R2 * e[1];
+                        t[1] += P * phi[it.k2] * cE * R2 * e[1];
                     }
                 } else {
-                    if (k3 == it.k1) t[1] += P * a.phi[it.k1] * cE * R2 * e[0];
-                    if (k3 == it.k2) t[2] += P * a.phi[it.k2] * cF * R2 * e[1];
-                    t[3] += P * a.phi[it.k1] * cG * R2 * e[2];
-                    if (k3 == it.k2) t[4] += P * a.psi[it.k1] * cH * R * e[3];
+                    if (k3 == it.k1) t[1] += P * phi[it.k1] * cE * R2 * e[0];
+                    if (k3 == it.k2) t[2] += P * phi[it.k2] * cF * R2 * e[1];
+                    t[3] += P * phi[it.k1] * cG * R2 * e[2];
+                    if (k3 == it.k2) t[4] += P * psi[it.k1] * cH * R * e[3];
                 }
             }
         }
@@ -501,7 +550,7 @@ __global__ void __launch_bounds__(THREADS) assemble_kernel(AssembleArgs a)
         for (int u = 0; u < 5; ++u) tot[u] += wf * tb[u];
     }
     if (tid == 0) {
-        const double P = a.power[cut];
+        const double P = power[cut];
         a.eta[q] = s2 / (P * P * P);
         if (a.sigma2) a.sigma2[q] = s2;
         if (a.terms)
@@ -511,22 +560,42 @@ __global__ void __launch_bounds__(THREADS) assemble_kernel(AssembleArgs a)
 
 }  // namespace
 
-hipError_t launch_region(const RegionArgs& a, int n_items, bool fp32, hipStream_t st)
+template <typename R, int MU>
+hipError_t launch_region_t(const RegionArgs& a, int blocks, hipStream_t st)
 {
-    const unsigned grid = (unsigned)n_items * (unsigned)a.n_groups;
-    if (grid == 0) return hipSuccess;
-    if (fp32) {
-        if (a.mu_method == 0)
-            hipLaunchKernelGGL((region_kernel<float, 0>), dim3(grid), dim3(THREADS), 0, st, a);
-        else
-            hipLaunchKernelGGL((region_kernel<float, 1>), dim3(grid), dim3(THREADS), 0, st, a);
-    } else {
-        if (a.mu_method == 0)
-            hipLaunchKernelGGL((region_kernel<double, 0>), dim3(grid), dim3(THREADS), 0, st, a);
-        else
-            hipLaunchKernelGGL((region_kernel<double, 1>), dim3(grid), dim3(THREADS), 0, st, a);
-    }
+    if (blocks > 0)
+        hipLaunchKernelGGL((region_queue_kernel<R, MU>), dim3(blocks), dim3(THREADS), 0, st, a);
+    else
+        hipLaunchKernelGGL((region_kernel<R, MU>), dim3(a.n_units), dim3(THREADS), 0, st, a);
     return hipGetLastError();
+}
+
+hipError_t launch_region(const RegionArgs& a, int blocks, bool fp32, hipStream_t st)
+{
+    if (a.n_units == 0) return hipSuccess;
+    if (fp32)
+        return a.mu_method == 0 ? launch_region_t<float, 0>(a, blocks, st) : launch_region_t<float, 1>(a, blocks, st);
+    return a.mu_method == 0 ? launch_region_t<double, 0>(a, blocks, st) : launch_region_t<double, 1>(a, blocks, st);
+}
+
+hipError_t launch_zero_counter(int* counter, hipStream_t st)
+{
+    hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(64), 0, st, counter);
+    return hipGetLastError();
+}
+
+// Resident blocks per CU of the queue kernel (occupancy query).
+int region_blocks_per_cu(bool fp32, int mu_method)
+{
+    int n = 0;
+    hipError_t e;
+    if (fp32)
+        e = mu_method == 0 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, region_queue_kernel<float, 0>, THREADS, 0)
+                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, region_queue_kernel<float, 1>, THREADS, 0);
+    else
+        e = mu_method == 0 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, region_queue_kernel<double, 0>, THREADS, 0)
+                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, region_queue_kernel<double, 1>, THREADS, 0);
+    return (e == hipSuccess && n > 0) ? n : 1;
 }
 
 hipError_t launch_egn(const EgnArgs& a, int n_delta, bool fp32, hipStream_t st)

@@ -1,0 +1,142 @@
+"""Batched evaluation: many uneven links through one work queue, graph capture
+and replay, re-capture on new numerics, and the launch-shape autotuner."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2412_11614_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FP64 = W.PREC_FP64
+FP32 = W.PREC_FP32_PHASE64
+
+
+def db(x, ref):
+    return 10.0 * np.log10(np.asarray(x) / np.asarray(ref))
+
+
+@pytest.fixture(scope="module")
+def engine():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2412_11614_amd import _lib
+    e = _lib.Engine(0)
+    yield e
+    e.close()
+
+
+def _links():
+    """Uneven links: channel counts, span counts, powers, formats, gain readings."""
+    out = [
+        W.small_mixed(seed=21, n_ch=5, n_spans=1, n_grid=24),
+        W.small_mixed(seed=22, n_ch=7, n_spans=3, n_grid=24),
+        W.small_mixed(seed=23, n_ch=4, n_spans=2, n_grid=24, gain_mode=W.GAIN_LOSS_ONLY),
+        W.small_mixed(seed=24, n_ch=6, n_spans=4, n_grid=24, rolloff=0.0),
+    ]
+    out[1].cuts = out[1].cuts[::2].copy()   # a CUT subset
+    return out
+
+
+def test_batch_matches_single_links_and_oracle(engine):
+    links = _links()
+    b = engine.batch(links)
+    nu = links[0].numerics
+    got = b.eval(nu, precision=FP64)
+    assert b.n_cuts == sum(len(w.cuts) for w in links)
+    off = b.cut_offset
+    for i, w in enumerate(links):
+        engine.load(w)
+        single = engine.eval_eta(nu, w.cuts, precision=FP64)["eta"]
+        seg = oracle.eval_cuts(w, method="segment")["eta"]
+        part = got[off[i]:off[i + 1]]
+        assert np.allclose(part, single, rtol=1e-13, atol=0), (i, part, single)
+        assert np.max(np.abs(db(part, seg))) <= 1e-9, i
+    b32 = b.eval(nu, precision=FP32)
+    for i, w in enumerate(links):
+        ref = oracle.eval_cuts(w, method="integral")["eta"]
+        assert np.max(np.abs(db(b32[off[i]:off[i + 1]], ref))) <= 1e-2
+    b.close()
+
+
+def test_graph_replays_match_eager(engine):
+    """The first call captures a graph; replays interleaved with other eager
+    work and synchronisations reproduce the eager (uncaptured) result."""
+    import torch
+    links = _links()
+    b = engine.batch(links)
+    nu = links[0].numerics
+    engine.set_profiling(True)            # profiling runs the launches eagerly
+    eager = b.eval(nu, precision=FP32)
+    engine.set_profiling(False)
+    x = torch.randn(1 << 20, device="cuda")
+    for rep in range(4):
+        r = b.eval(nu, precision=FP32)     # capture on the first pass, replay after
+        assert np.array_equal(r, eager), rep
+        engine.load(links[rep % len(links)])
+        engine.eval_eta(nu, links[rep % len(links)].cuts, precision=FP64)
+        x = (x * 1.0001).contiguous()
+        torch.cuda.synchronize()
+    b.close()
+
+
+def test_device_output_and_recapture_on_new_numerics(engine):
+    import torch
+    links = _links()
+    b = engine.batch(links)
+    nu = links[0].numerics
+    out = torch.zeros(b.n_cuts, dtype=torch.float64, device="cuda")
+    b.eval_dev(nu, out, precision=FP64)
+    torch.cuda.synchronize()
+    first = out.cpu().numpy().copy()
+    assert np.allclose(first, b.eval(nu, precision=FP64), rtol=0, atol=0)
+    # different grid: the work list is rebuilt and the graph captured again
+    got16 = b.eval(nu, precision=FP64, n=16)
+    off = b.cut_offset
+    for i, w in enumerate(links):
+        engine.load(w)
+        single = engine.eval_eta(nu, w.cuts, precision=FP64, n=16)["eta"]
+        assert np.allclose(got16[off[i]:off[i + 1]], single, rtol=1e-13, atol=0)
+    again = b.eval(nu, precision=FP64)
+    assert np.array_equal(again, first)
+    b.close()
+
+
+def test_autotune_picks_a_shape_and_caches_it(engine, tmp_path):
+    links = _links()
+    b = engine.batch(links)
+    nu = links[0].numerics
+    engine.set_profiling(True)
+    ref = b.eval(nu, precision=FP32)
+    engine.set_profiling(False)
+    cache = str(tmp_path / "tune.json")
+    t = b.autotune(nu, cache, precision=FP32)
+    assert t["mode"] in (0, 1) and t["strips"] >= 1
+    entries = json.load(open(cache))
+    assert len(entries) == 1 and entries[0]["ms"] > 0
+    got = b.eval(nu, precision=FP32)
+    assert np.allclose(got, ref, rtol=1e-12, atol=0)
+    # a second batch of the same shape reuses the cached choice
+    b2 = engine.batch(links)
+    t2 = b2.autotune(nu, cache, precision=FP32)
+    assert t2 == t
+    assert np.allclose(b2.eval(nu, precision=FP32), ref, rtol=1e-12, atol=0)
+    b.close()
+    b2.close()
+
+
+def test_batch_rejects_bad_links(engine):
+    from paper_2412_11614_amd import _lib
+    links = _links()
+    links[2].spectrum.power_w[:] = 0.0
+    with pytest.raises(_lib.IsrsError) as ei:
+        engine.batch(links)
+    assert ei.value.code == _lib.ISRS_E_SPECTRUM and "link 2" in str(ei.value)
+    links = _links()
+    links[1].link.spans["length_km"][0] = -1.0
+    with pytest.raises(_lib.IsrsError) as ei:
+        engine.batch(links)
+    assert ei.value.code == _lib.ISRS_E_LINK
