@@ -75,6 +75,55 @@ def cpu_baseline(wl, n_squares, seed=0):
                        f"{wall:.1f} s wall on {threads} threads, scaled by squares per CUT")}
 
 
+def batched_leg(eng, n_links, n_plain, W, torch):
+    """Uneven-link workload in one queue launch per chunk, replayed from a
+    captured graph, against the plain one-link-at-a-time path."""
+    links = W.batch_links(n_links=n_links)
+    nu = links[0].numerics                       # 64 x 64, FP32 integrand / FP64 phase
+    b = eng.batch(links)
+    eta_b = torch.empty(b.n_cuts, dtype=torch.float64, device="cuda")
+    log(f"batched: {n_links} links, {b.n_cuts} CUTs: warm-up (plan + eager run), capture")
+    t0 = time.perf_counter()
+    b.eval_dev(nu, eta_b)
+    torch.cuda.synchronize()
+    t_first = time.perf_counter() - t0
+    b.eval_dev(nu, eta_b)                        # capture the graph
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.eval_dev(nu, eta_b)                        # timed replay
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    eta_batch = eta_b.cpu().numpy()
+    # plain path on the first n_plain links, same numerics
+    n_plain = min(n_plain, n_links)
+    off = b.cut_offset
+    cuts_plain = int(off[n_plain])
+    eta_plain = torch.empty(max(1, max(len(w.cuts) for w in links[:n_plain])), dtype=torch.float64, device="cuda")
+    agree = 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i, w in enumerate(links[:n_plain]):
+        eng.load(w)
+        eng.eval_eta_dev(nu, w.cuts, eta_plain)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    for i, w in enumerate(links[:n_plain]):
+        eng.load(w)
+        eng.eval_eta_dev(nu, w.cuts, eta_plain)
+        torch.cuda.synchronize()
+        ref = eta_plain[:len(w.cuts)].cpu().numpy()
+        agree = max(agree, float(np.max(np.abs(10 * np.log10(eta_batch[off[i]:off[i + 1]] / ref)))))
+    b.close()
+    return {"workload": (f"{n_links} links: 20-100 active of 100 x 96 GBd / 100 GHz slots, P U[-3,3] dBm, "
+                         f"1-30 spans U[50,120] km, alpha and Cr per link (seed 3), 64x64 per square, "
+                         f"all active channels under test"),
+            "n_cut": int(b.n_cuts), "value": b.n_cuts / t_batch, "unit": "CUT/s",
+            "ms_per_step": 1e3 * t_batch, "first_call_s": t_first,
+            "plain_path": {"links": n_plain, "n_cut": cuts_plain, "value": cuts_plain / t_plain, "unit": "CUT/s"},
+            "speedup_vs_plain": (b.n_cuts / t_batch) / (cuts_plain / t_plain),
+            "max_abs_db_batch_vs_plain": agree}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +133,10 @@ def main():
     ap.add_argument("--cpu-squares", type=int, default=48)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--batch-links", type=int, default=512,
+                    help="links of the batched leg (0 = skip)")
+    ap.add_argument("--plain-links", type=int, default=48,
+                    help="links of the batch evaluated one by one on the plain path for comparison")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the steps, copy this many MiB device-to-device (counter calibration)")
     ap.add_argument("--traffic-bytes", type=float, default=None,
@@ -182,6 +235,8 @@ def main():
         out["accuracy"] = {"fp32_vs_fp64_max_abs_db": float(err.max()), "fp32_vs_fp64_mean_abs_db": float(err.mean()),
                            "within_0p01_db": bool(err.max() <= 0.01)}
         out["fp64_value"] = n_cut / t64
+    if args.batch_links > 0:
+        out["batched"] = batched_leg(eng, args.batch_links, args.plain_links, W, torch)
     eng.close()
 
     if args.calib_copy_mib:
