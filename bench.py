@@ -157,8 +157,9 @@ def main():
     wl = W.cl_100ch_10span(n_grid=args.grid, precision=W.PREC_FP32_PHASE64)
     cuts = wl.cuts
     n_cut = len(cuts)
-    stream = torch.cuda.current_stream()
-    eng = _lib.Engine(0, stream=stream.cuda_stream)
+    stream = torch.cuda.Stream()          # shared with the library: torch and the kernels stay ordered
+    torch.cuda.set_stream(stream)
+    eng = _lib.Engine(0, stream=stream)
     eng.load(wl)
     eta = torch.empty(n_cut, dtype=torch.float64, device=dev)
     s2 = torch.empty(n_cut, dtype=torch.float64, device=dev)

@@ -233,6 +233,98 @@ int32_t isrs_autotune(isrs_ctx* ctx, isrs_batch* batch, const isrs_numerics* num
 int32_t isrs_batch_get_tuning(const isrs_batch* batch, int32_t* mode, int32_t* blocks_per_cu, int32_t* sort,
                               int32_t* strips);
 
+/* ------------------------------------------------------------------------
+ * Learned surrogate of the per-span FWM efficiency (an MLP ensemble).
+ *
+ * Query point (one span of one link at one (f1, f2, f)): 16 floats, of
+ * which entries 0..8 hold 9 physical features scaled linearly from the
+ * sampling box to [-1, 1] (entries 9..15 are ignored):
+ *   f1, f2, f      absolute frequencies from the grid centre, [-5, 5] THz
+ *   L              span length, [80, 100] km
+ *   alpha          [0.18, 0.22] dB/km
+ *   beta2, beta3   [-23, -20] ps^2/km, [0.10, 0.16] ps^3/km
+ *   Cr             [0.020, 0.035] 1/(W km THz)
+ *   Ptot           [17, 23] dBm (ISRS profile of Eq. 25, B_tot = 10 THz)
+ * Network input: those 9 values and 7 derived in FP64 from them, with chi of
+ * Eq. 24, Delta = L / ceil(L / 1 km) and |beta| = sqrt(alpha^2 + chi^2):
+ * cos(chi L), sin(chi L), ln(1 + |chi| / alpha) / 8 - 1, alpha / |beta|,
+ * chi / |beta|, cos(chi Delta), sin(chi Delta).
+ * Target: y = ln(|mu_s|^2 / L_eff^2) of the segment closed form (Eqs. 7-10,
+ * dz = 1 km).  The network learns the residual r = y - y6 over the closed
+ * form without ISRS (Eq. 6); predictions are y6 + r.
+ * Network per member: 16 -> 256 -> 256 -> 256 -> 256 -> 1, SiLU, BF16
+ * weights and activations with FP32 accumulation on MFMA, FP32 master
+ * weights and Adam.
+ * ------------------------------------------------------------------------ */
+typedef struct isrs_surrogate isrs_surrogate;
+
+typedef struct {
+    int32_t steps;       /* optimiser steps per member */
+    int32_t batch;       /* minibatch rows, multiple of 64 */
+    float lr;            /* Adam step size */
+    float beta1, beta2, eps;
+    int32_t member;      /* member to train, -1 = all */
+} isrs_train_opts;
+
+#define ISRS_SUR_FEATURES 16  /* padded input width */
+#define ISRS_SUR_HIDDEN 256
+
+/* Creates an ensemble of n_members (1..16) with seeded initial weights. */
+int32_t isrs_surrogate_create(isrs_ctx* ctx, int32_t n_members, uint64_t seed, isrs_surrogate** out);
+int32_t isrs_surrogate_destroy(isrs_surrogate* sur);
+
+/* Draws n query points from the feature box (a channel-pair square of a
+ * 100-channel, 100 GHz grid whose product f1 + f2 - f falls in a channel, a
+ * uniform point of it, f uniform over the CUT's band; span parameters
+ * uniform) with a counter-based generator (SplitMix64) keyed by seed, and
+ * labels them with the closed form in FP64.  x_dev: device [n*16] scaled features;
+ * r_dev: device [n] residual targets; y6_dev: device [n] or NULL. */
+int32_t isrs_surrogate_datagen(isrs_ctx* ctx, int64_t n, uint64_t seed, float* x_dev, float* r_dev,
+                               float* y6_dev);
+
+/* Adam on the mean squared error of the normalised residual
+ * t = (r - shift) / scale for opts->steps minibatches per member (rows drawn
+ * in order, wrapping).  shift and scale are the mean and standard deviation
+ * of r_dev[0, n) at the first training call, kept for the surrogate's life
+ * (and in checkpoints); the network's raw output o predicts t, and
+ * predictions are shift + scale * o.  loss_out (host, nullable) receives each
+ * trained member's mean loss over its last 16 steps, in units of r^2. */
+int32_t isrs_surrogate_train(isrs_ctx* ctx, isrs_surrogate* sur, const float* x_dev, const float* r_dev, int64_t n,
+                             const isrs_train_opts* opts, double* loss_out);
+
+/* Ensemble prediction of the residual: mean_dev and spread_dev (max - min
+ * over members, in ln units), device [n]; either may be NULL. */
+int32_t isrs_surrogate_predict(isrs_ctx* ctx, isrs_surrogate* sur, const float* x_dev, int64_t n, float* mean_dev,
+                               float* spread_dev);
+
+/* y = ln(|mu|^2 / L_eff^2) for n query points: the ensemble where its
+ * spread is at most spread_db_threshold (in dB of |mu|^2), the closed form
+ * (FP64, Eqs. 7-10) elsewhere.  y_dev device [n]; n_fallback (host,
+ * nullable) counts the closed-form points.  threshold < 0: all closed form. */
+int32_t isrs_surrogate_eval_points(isrs_ctx* ctx, isrs_surrogate* sur, const float* x_dev, int64_t n,
+                                   double spread_db_threshold, float* y_dev, int64_t* n_fallback);
+
+/* Closed form only, same query points and output as above. */
+int32_t isrs_closed_form_points(isrs_ctx* ctx, const float* x_dev, int64_t n, float* y_dev);
+
+/* Parameters of one member as FP32 host arrays in the order W1 [16x256],
+ * b1 [256], W2, b2, W3, b3, W4 [256x256] each with b, w5 [256], b5 [1]
+ * (row-major, input index first).  n_params = 201,985. */
+int32_t isrs_surrogate_num_params(int64_t* n_params);
+int32_t isrs_surrogate_get_target_scale(const isrs_surrogate* sur, double* shift, double* scale);
+int32_t isrs_surrogate_get_params(isrs_surrogate* sur, int32_t member, float* params);
+int32_t isrs_surrogate_set_params(isrs_ctx* ctx, isrs_surrogate* sur, int32_t member, const float* params);
+
+/* Gradient of mean((o - t)^2) over n rows (no update), t the normalised
+ * residual above, same layout as the parameters; grads host [n_params],
+ * loss host (normalised units). */
+int32_t isrs_surrogate_grad(isrs_ctx* ctx, isrs_surrogate* sur, int32_t member, const float* x_dev,
+                            const float* r_dev, int64_t n, float* grads, double* loss);
+
+/* Checkpoint: weights, Adam moments, step counters and seed. */
+int32_t isrs_surrogate_save(isrs_surrogate* sur, const char* path);
+int32_t isrs_surrogate_load(isrs_ctx* ctx, isrs_surrogate* sur, const char* path);
+
 /* Pure host checks used by the set/eval calls (no device needed). */
 int32_t isrs_validate_spectrum(const isrs_spectrum* spectrum);
 int32_t isrs_validate_link(const isrs_span* spans, int32_t n_spans, int32_t gain_mode);

@@ -35,7 +35,14 @@ EXPORTED = [
     "isrs_validate_link", "isrs_validate_numerics", "isrs_version",
     "isrs_batch_create", "isrs_batch_destroy", "isrs_batch_num_cuts", "isrs_batch_eval",
     "isrs_batch_eval_dev", "isrs_autotune", "isrs_batch_get_tuning",
+    "isrs_surrogate_create", "isrs_surrogate_destroy", "isrs_surrogate_datagen", "isrs_surrogate_train",
+    "isrs_surrogate_predict", "isrs_surrogate_eval_points", "isrs_closed_form_points",
+    "isrs_surrogate_num_params", "isrs_surrogate_get_params", "isrs_surrogate_set_params",
+    "isrs_surrogate_grad", "isrs_surrogate_save", "isrs_surrogate_load", "isrs_surrogate_get_target_scale",
 ]
+
+SUR_FEATURES = 16
+SUR_HIDDEN = 256
 
 
 class IsrsError(RuntimeError):
@@ -69,6 +76,11 @@ class LinkBatch_c(C.Structure):
                 ("gain_mode", C.POINTER(C.c_int32)), ("power_w", C.POINTER(C.c_double)),
                 ("phi", C.POINTER(C.c_double)), ("psi", C.POINTER(C.c_double)),
                 ("spans", C.c_void_p)]
+
+
+class TrainOpts_c(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("eps", C.c_float), ("member", C.c_int32)]
 
 
 class Stats_c(C.Structure):
@@ -118,6 +130,21 @@ def lib():
     L.isrs_batch_eval_dev.argtypes = [vp, vp, C.POINTER(Numerics_c), vp]
     L.isrs_autotune.argtypes = [vp, vp, C.POINTER(Numerics_c), C.c_char_p]
     L.isrs_batch_get_tuning.argtypes = [vp, ip, ip, ip, ip]
+    fp = C.POINTER(C.c_float)
+    L.isrs_surrogate_create.argtypes = [vp, C.c_int32, C.c_uint64, C.POINTER(vp)]
+    L.isrs_surrogate_destroy.argtypes = [vp]
+    L.isrs_surrogate_datagen.argtypes = [vp, C.c_int64, C.c_uint64, vp, vp, vp]
+    L.isrs_surrogate_train.argtypes = [vp, vp, vp, vp, C.c_int64, C.POINTER(TrainOpts_c), dp]
+    L.isrs_surrogate_predict.argtypes = [vp, vp, vp, C.c_int64, vp, vp]
+    L.isrs_surrogate_eval_points.argtypes = [vp, vp, vp, C.c_int64, C.c_double, vp, C.POINTER(C.c_int64)]
+    L.isrs_closed_form_points.argtypes = [vp, vp, C.c_int64, vp]
+    L.isrs_surrogate_num_params.argtypes = [C.POINTER(C.c_int64)]
+    L.isrs_surrogate_get_params.argtypes = [vp, C.c_int32, fp]
+    L.isrs_surrogate_set_params.argtypes = [vp, vp, C.c_int32, fp]
+    L.isrs_surrogate_grad.argtypes = [vp, vp, C.c_int32, vp, vp, C.c_int64, fp, dp]
+    L.isrs_surrogate_save.argtypes = [vp, C.c_char_p]
+    L.isrs_surrogate_load.argtypes = [vp, vp, C.c_char_p]
+    L.isrs_surrogate_get_target_scale.argtypes = [vp, dp, dp]
     for name in EXPORTED:
         f = getattr(L, name)
         if f.restype is C.c_int:  # default
@@ -274,6 +301,99 @@ class Batch:
         return {"mode": v[0].value, "blocks_per_cu": v[1].value, "sort": v[2].value, "strips": v[3].value}
 
 
+def _fp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def _dev(t, dtype, n):
+    """Device pointer of a contiguous torch GPU tensor with at least n elements."""
+    if t is None:
+        return None
+    if str(t.dtype) != dtype or not t.is_cuda or not t.is_contiguous() or t.numel() < n:
+        raise ValueError(f"expected a contiguous {dtype} GPU tensor with at least {n} elements")
+    return C.c_void_p(t.data_ptr())
+
+
+class Surrogate:
+    """MLP ensemble of the per-span FWM efficiency (isrs_surrogate_*).
+
+    Query points are float32 device tensors [n, 16] of scaled features."""
+
+    def __init__(self, engine, n_members=4, seed=0):
+        self._e = engine
+        self._h = C.c_void_p()
+        engine._check(engine._L.isrs_surrogate_create(engine._h, int(n_members), int(seed), C.byref(self._h)))
+        self.n_members = int(n_members)
+        n = C.c_int64()
+        engine._check(engine._L.isrs_surrogate_num_params(C.byref(n)))
+        self.n_params = int(n.value)
+
+    def close(self):
+        if self._h:
+            self._e._L.isrs_surrogate_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def train(self, x, r, steps, batch=1024, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, member=-1):
+        n = r.numel()
+        o = TrainOpts_c(int(steps), int(batch), float(lr), float(beta1), float(beta2), float(eps), int(member))
+        loss = np.zeros(self.n_members)
+        self._e._check(self._e._L.isrs_surrogate_train(self._e._h, self._h, _dev(x, "torch.float32", 16 * n),
+                                                       _dev(r, "torch.float32", n), n, C.byref(o), _dp(loss)))
+        return loss
+
+    def predict(self, x, mean=None, spread=None):
+        n = x.numel() // SUR_FEATURES
+        self._e._check(self._e._L.isrs_surrogate_predict(self._e._h, self._h, _dev(x, "torch.float32", 16 * n), n,
+                                                         _dev(mean, "torch.float32", n),
+                                                         _dev(spread, "torch.float32", n)))
+
+    def eval_points(self, x, y, spread_db_threshold):
+        n = x.numel() // SUR_FEATURES
+        nf = C.c_int64()
+        self._e._check(self._e._L.isrs_surrogate_eval_points(
+            self._e._h, self._h, _dev(x, "torch.float32", 16 * n), n, float(spread_db_threshold),
+            _dev(y, "torch.float32", n), C.byref(nf)))
+        return int(nf.value)
+
+    def get_params(self, member):
+        p = np.zeros(self.n_params, dtype=np.float32)
+        self._e._check(self._e._L.isrs_surrogate_get_params(self._h, int(member), _fp(p)))
+        return p
+
+    def set_params(self, member, params):
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+        if p.size != self.n_params:
+            raise ValueError("wrong parameter count")
+        self._e._check(self._e._L.isrs_surrogate_set_params(self._e._h, self._h, int(member), _fp(p)))
+
+    def grad(self, member, x, r):
+        n = r.numel()
+        g = np.zeros(self.n_params, dtype=np.float32)
+        loss = C.c_double()
+        self._e._check(self._e._L.isrs_surrogate_grad(self._e._h, self._h, int(member),
+                                                      _dev(x, "torch.float32", 16 * n),
+                                                      _dev(r, "torch.float32", n), n, _fp(g), C.byref(loss)))
+        return g, loss.value
+
+    def target_scale(self):
+        """(shift, scale): the network's raw output predicts (r - shift) / scale."""
+        a, b = C.c_double(), C.c_double()
+        self._e._check(self._e._L.isrs_surrogate_get_target_scale(self._h, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def save(self, path):
+        self._e._check(self._e._L.isrs_surrogate_save(self._h, str(path).encode()))
+
+    def load(self, path):
+        self._e._check(self._e._L.isrs_surrogate_load(self._e._h, self._h, str(path).encode()))
+
+
 @dataclass
 class Stats:
     region_ms: float
@@ -292,9 +412,18 @@ class Engine:
     """One library context on one GPU.  Mirrors the C-ABI calls."""
 
     def __init__(self, device: int = 0, stream=None):
+        """stream: None (the library's own stream), a hipStream_t handle or a
+        torch.cuda.Stream.  The null stream cannot be shared: a NULL handle
+        means "own stream" in the C-ABI, whose work would then not be ordered
+        with the caller's."""
         L = lib()
         self._h = C.c_void_p()
-        s = C.c_void_p(int(stream)) if stream is not None else None
+        s = None
+        if stream is not None:
+            h = int(getattr(stream, "cuda_stream", stream))
+            if h == 0:
+                raise ValueError("pass a created stream (e.g. torch.cuda.Stream()) or None, not the null stream")
+            s = C.c_void_p(h)
         rc = L.isrs_create(C.byref(self._h), int(device), s)
         if rc != ISRS_OK:
             raise IsrsError(rc, L.isrs_last_error(None).decode())
@@ -388,6 +517,20 @@ class Engine:
 
     def batch(self, workloads):
         return Batch(self, workloads)
+
+    def surrogate(self, n_members=4, seed=0):
+        return Surrogate(self, n_members, seed)
+
+    def surrogate_datagen(self, x, r, seed, y6=None):
+        """Fills x [n, 16], r [n] (and y6 [n]) with labelled query points."""
+        n = r.numel()
+        self._check(self._L.isrs_surrogate_datagen(self._h, n, int(seed), _dev(x, "torch.float32", 16 * n),
+                                                   _dev(r, "torch.float32", n), _dev(y6, "torch.float32", n)))
+
+    def closed_form_points(self, x, y):
+        n = x.numel() // SUR_FEATURES
+        self._check(self._L.isrs_closed_form_points(self._h, _dev(x, "torch.float32", 16 * n), n,
+                                                    _dev(y, "torch.float32", n)))
 
     def stats(self) -> Stats:
         s = Stats_c()

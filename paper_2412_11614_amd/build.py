@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libisrs_egn.so")
-SOURCES = ["isrs_api.cpp", "isrs_kernels.hip"]
+SOURCES = ["isrs_api.cpp", "isrs_kernels.hip", "isrs_surrogate.hip"]
 
 # Packed FP32 instructions stay off: the compiler may not form v_pk_* FP32 ops.
 HIPFLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",

@@ -1048,6 +1048,13 @@ bool write_cache(const char* path, const std::map<std::string, std::vector<doubl
 
 }  // namespace
 
+namespace isrs {
+hipStream_t ctx_stream(isrs_ctx* c) { return c->stream; }
+int ctx_device(const isrs_ctx* c) { return c->device; }
+int ctx_num_cu(const isrs_ctx* c) { return c->n_cu; }
+int32_t ctx_fail(isrs_ctx* c, int32_t code, const char* msg) { return fail(c, code, msg); }
+}  // namespace isrs
+
 extern "C" {
 
 const char* isrs_version(void) { return "isrs-egn 0.2 (gfx950)"; }

@@ -146,3 +146,12 @@ hipError_t launch_assemble(const AssembleArgs& a, hipStream_t st);
 int region_blocks_per_cu(bool fp32, int mu_method);
 
 }  // namespace isrs
+
+// Context accessors for the surrogate's host code (isrs_surrogate.hip).
+struct isrs_ctx;
+namespace isrs {
+hipStream_t ctx_stream(isrs_ctx* c);
+int ctx_device(const isrs_ctx* c);
+int ctx_num_cu(const isrs_ctx* c);
+int32_t ctx_fail(isrs_ctx* c, int32_t code, const char* msg);
+}  // namespace isrs

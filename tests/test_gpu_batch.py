@@ -89,6 +89,7 @@ def test_device_output_and_recapture_on_new_numerics(engine):
     b = engine.batch(links)
     nu = links[0].numerics
     out = torch.zeros(b.n_cuts, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()              # the fill runs on torch's stream, the batch on the library's
     b.eval_dev(nu, out, precision=FP64)
     torch.cuda.synchronize()
     first = out.cpu().numpy().copy()

@@ -1,0 +1,221 @@
+"""Surrogate on the GPU: training labels against the oracle's closed form,
+MFMA gradients against the FP64 reference network, training, ensemble
+fallback, checkpoint and resume."""
+import numpy as np
+import pytest
+
+from oracle import surrogate as S
+
+pytestmark = pytest.mark.gpu
+
+N_DATA = 70_000          # more than one 65,536-row forward chunk, ragged tail
+DB = 10.0 / np.log(10.0)
+
+
+@pytest.fixture(scope="module")
+def engine():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2412_11614_amd import _lib
+    st = torch.cuda.Stream()            # torch work and library work ordered on one stream
+    torch.cuda.set_stream(st)
+    e = _lib.Engine(0, stream=st)
+    yield e
+    torch.cuda.synchronize()
+    e.close()
+    torch.cuda.set_stream(torch.cuda.default_stream())
+
+
+def _data(engine, n, seed):
+    import torch
+    x = torch.empty(n, 16, device="cuda")
+    r = torch.empty(n, device="cuda")
+    y6 = torch.empty(n, device="cuda")
+    engine.surrogate_datagen(x, r, seed, y6=y6)
+    return x, r, y6
+
+
+@pytest.fixture(scope="module")
+def data(engine):
+    return _data(engine, N_DATA, seed=11)
+
+
+def test_datagen_points_and_labels(engine, data):
+    x, r, y6 = (t.cpu().numpy() for t in data)
+    assert np.all(np.abs(x[:, :S.NF]) <= 1.0) and np.all(x[:, S.NF:] == 0.0)
+    phys = S.decode(x)
+    # f1 + f2 - f falls in a channel of the 100 x 100 GHz grid for (almost) every point
+    f3 = phys[:, 0] + phys[:, 1] - phys[:, 2]
+    u = f3 / 0.1 + 49.5
+    inside = (np.abs(u - np.rint(u)) * 0.1 <= 0.5 * 0.09984 + 1e-6) & (np.rint(u) >= 0) & (np.rint(u) <= 99)
+    assert inside.mean() > 0.999
+    # a uniform spread over the span parameters
+    for j in range(3, S.NF):
+        assert abs(np.mean(x[:, j])) < 0.02, j
+    rng = np.random.default_rng(0)
+    for i in rng.choice(len(r), size=40, replace=False):
+        y_ref, y6_ref = S.target(phys[i])
+        assert abs(y6[i] - y6_ref) <= 2e-6 * max(1.0, abs(y6_ref)), (i, phys[i])
+        assert abs(r[i] - (y_ref - y6_ref)) <= 2e-6 * max(1.0, abs(y_ref)), (i, phys[i])
+    # same seed, same points; another seed, other points
+    x2, r2, _ = _data(engine, 1000, seed=11)
+    assert np.array_equal(x2.cpu().numpy(), x[:1000]) and np.array_equal(r2.cpu().numpy(), r[:1000])
+    x3, _, _ = _data(engine, 1000, seed=12)
+    assert not np.array_equal(x3.cpu().numpy(), x[:1000])
+
+
+def test_closed_form_points(engine, data):
+    import torch
+    x, r, y6 = data
+    y = torch.empty_like(r)
+    engine.closed_form_points(x, y)
+    y, r, y6 = y.cpu().numpy(), r.cpu().numpy(), y6.cpu().numpy()
+    assert np.allclose(y, r.astype(np.float64) + y6, rtol=1e-6, atol=1e-6)
+
+
+def test_gradient_matches_fp64_reference(engine, data):
+    x, r, _ = data
+    s = engine.surrogate(n_members=2, seed=5)
+    s.train(x, r, steps=3, batch=256)             # sets the target scale, moves off the initial point
+    shift, scale = s.target_scale()
+    assert abs(shift - float(r.double().mean())) <= 1e-6 * max(1.0, abs(shift))
+    assert abs(scale - float(r.double().std(unbiased=False))) <= 1e-6 * scale
+    n = 512
+    xs, rs = x[:n].contiguous(), r[:n].contiguous()
+    xn, rn = S.features(xs.cpu().numpy()), rs.cpu().numpy().astype(np.float64)
+    tn = (rn - shift) / scale
+    for member in (0, 1):
+        p = s.get_params(member).astype(np.float64)
+        g, loss = s.grad(member, xs, rs)
+        loss_ref, g_ref = S.loss_and_grad(p, xn, tn)
+        # BF16 operands (8-bit significand) through four layers: percent-level agreement
+        assert abs(loss - loss_ref) <= 2e-2 * loss_ref, (loss, loss_ref)
+        lay, _ = S.layout()
+        for name, (o, shp) in lay.items():
+            k = int(np.prod(shp))
+            a, b = g[o:o + k].astype(np.float64), g_ref[o:o + k]
+            rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+            cos = a @ b / max(np.linalg.norm(a) * np.linalg.norm(b), 1e-30)
+            assert rel <= 5e-2 and cos >= 0.998, (member, name, rel, cos)
+    s.close()
+
+
+def test_training_reduces_error_and_beats_eq6(engine, data):
+    import torch
+    x, r, _ = data
+    s = engine.surrogate(n_members=2, seed=7)
+    var0 = float(torch.var(r).item())
+    loss = s.train(x, r, steps=600, batch=1024, lr=1e-3)
+    assert np.all(loss < 0.05 * var0), (loss, var0)
+    # held-out points: the ensemble against the closed form, in dB of |mu|^2
+    xh, rh, y6h = _data(engine, 8192, seed=99)
+    yh = torch.empty_like(rh)
+    assert s.eval_points(xh, yh, float("inf")) == 0
+    ycf = torch.empty_like(rh)
+    engine.closed_form_points(xh, ycf)
+    err = DB * (yh - ycf).double().cpu().numpy()
+    base = DB * (y6h - ycf).double().cpu().numpy()            # Eq. 6 alone, no ISRS
+    rms, rms0 = np.sqrt(np.mean(err ** 2)), np.sqrt(np.mean(base ** 2))
+    assert rms < 0.2 * rms0, (rms, rms0)
+    s.close()
+
+
+def test_fallback_thresholds(engine, data):
+    import torch
+    x, r, y6 = data
+    s = engine.surrogate(n_members=3, seed=8)
+    s.train(x, r, steps=100, batch=512, lr=1e-3)
+    n = 5000
+    xs = x[:n].contiguous()
+    mean = torch.empty(n, device="cuda")
+    spread = torch.empty(n, device="cuda")
+    s.predict(xs, mean, spread)
+    ycf = torch.empty(n, device="cuda")
+    engine.closed_form_points(xs, ycf)
+    y = torch.empty(n, device="cuda")
+    # threshold < 0: every point falls back, identical to the closed form
+    assert s.eval_points(xs, y, -1.0) == n
+    assert torch.equal(y, ycf)
+    # no fallback: y6 + ensemble mean
+    assert s.eval_points(xs, y, float("inf")) == 0
+    assert np.allclose(y.cpu().numpy(), (y6[:n] + mean).cpu().numpy(), rtol=2e-6, atol=2e-6)
+    # threshold between two spreads: exactly the points above it fall back
+    sp_db = np.sort(spread.double().cpu().numpy() * DB)
+    thr = 0.5 * (sp_db[n // 2] + sp_db[n // 2 + 1])
+    above = spread.double().cpu().numpy() * DB > thr
+    nf = s.eval_points(xs, y, thr)
+    assert nf == int(above.sum())
+    yn, ycfn = y.cpu().numpy(), ycf.cpu().numpy()
+    assert np.array_equal(yn[above], ycfn[above])
+    assert np.allclose(yn[~above], (y6[:n] + mean).cpu().numpy()[~above], rtol=2e-6, atol=2e-6)
+    s.close()
+
+
+def test_predict_rows_are_independent(engine, data):
+    """A ragged batch and a prefix of a larger one give identical rows."""
+    import torch
+    x, _, _ = data
+    s = engine.surrogate(n_members=2, seed=9)
+    m_big = torch.empty(N_DATA, device="cuda")
+    s.predict(x, m_big, None)
+    m_small = torch.empty(1000, device="cuda")
+    s.predict(x[:1000].contiguous(), m_small, None)
+    assert torch.equal(m_big[:1000], m_small)
+    tail = x[N_DATA - 77:].contiguous()
+    m_tail = torch.empty(77, device="cuda")
+    s.predict(tail, m_tail, None)
+    assert torch.equal(m_big[N_DATA - 77:], m_tail)
+    s.close()
+
+
+def test_checkpoint_resume(engine, data, tmp_path):
+    x, r, _ = data
+    a = engine.surrogate(n_members=2, seed=1)
+    a.train(x, r, steps=30, batch=256, lr=1e-3)
+    path = tmp_path / "sur.bin"
+    a.save(path)
+    b = engine.surrogate(n_members=2, seed=2)
+    b.load(path)
+    for m in (0, 1):
+        assert np.array_equal(a.get_params(m), b.get_params(m))
+    la = a.train(x, r, steps=20, batch=256, lr=1e-3)
+    lb = b.train(x, r, steps=20, batch=256, lr=1e-3)
+    assert np.array_equal(la, lb)
+    for m in (0, 1):
+        assert np.array_equal(a.get_params(m), b.get_params(m))
+    c = engine.surrogate(n_members=3, seed=1)
+    from paper_2412_11614_amd import _lib
+    with pytest.raises(_lib.IsrsError):
+        c.load(path)                      # member count differs
+    a.close()
+    b.close()
+    c.close()
+
+
+def test_parameter_roundtrip_and_validation(engine, data):
+    import torch
+    from paper_2412_11614_amd import _lib
+    x, r, _ = data
+    s = engine.surrogate(n_members=1, seed=3)
+    p = S.init_like(42).astype(np.float32)
+    s.set_params(0, p)
+    assert np.array_equal(s.get_params(0), p)
+    # the device network follows the new parameters: compare with the reference forward
+    n = 256
+    mean = torch.empty(n, device="cuda")
+    s.predict(x[:n].contiguous(), mean, None)
+    ref = S.forward(p.astype(np.float64), S.features(x[:n].cpu().numpy()))
+    scale = max(1.0, float(np.max(np.abs(ref))))
+    assert np.max(np.abs(mean.cpu().numpy() - ref)) <= 3e-2 * scale
+    bad = p.copy()
+    bad[10] = np.nan
+    with pytest.raises(_lib.IsrsError) as ei:
+        s.set_params(0, bad)
+    assert ei.value.code == _lib.ISRS_E_NUMERIC
+    with pytest.raises(_lib.IsrsError):
+        s.eval_points(x[:64].contiguous(), torch.empty(64, device="cuda"), float("nan"))
+    with pytest.raises(_lib.IsrsError):
+        s.train(x, r, steps=1, batch=100)        # not a multiple of 64
+    with pytest.raises(_lib.IsrsError):
+        engine.surrogate(n_members=0)
+    s.close()
