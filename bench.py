@@ -124,6 +124,71 @@ def batched_leg(eng, n_links, n_plain, W, torch):
             "max_abs_db_batch_vs_plain": agree}
 
 
+def surrogate_leg(eng, n_points, torch, train_rows=1 << 20, members=4):
+    """Ensemble surrogate of the per-span FWM factor: training time, held-out
+    error against the closed form, and throughput of inference with fallback
+    (0.01 dB spread threshold) against the closed form on the same points."""
+    db = 10.0 / np.log(10.0)
+
+    def data(n, seed):
+        x = torch.empty(n, 16, device="cuda")
+        r = torch.empty(n, device="cuda")
+        y6 = torch.empty(n, device="cuda")
+        eng.surrogate_datagen(x, r, seed, y6=y6)
+        return x, r, y6
+
+    x, r, _ = data(train_rows, 4)
+    s = eng.surrogate(members, seed=4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.train(x, r, steps=1500, batch=1024, lr=1e-3)
+    loss = s.train(x, r, steps=500, batch=1024, lr=3e-4)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del x, r
+    xh, _, _ = data(8192, 1000)
+    ycf = torch.empty(8192, device="cuda")
+    eng.closed_form_points(xh, ycf)
+    yh = torch.empty(8192, device="cuda")
+    res = {}
+    for thr in (float("inf"), 0.01):
+        nf = s.eval_points(xh, yh, thr)
+        err = db * (yh - ycf).double().cpu().numpy()
+        res["no_fallback" if thr == float("inf") else "thr_0p01_db"] = {
+            "rms_db": float(np.sqrt(np.mean(err ** 2))), "max_abs_db": float(np.abs(err).max()),
+            "fallback_fraction": nf / 8192}
+    xb, _, y6b = data(n_points, 5)
+    yb = torch.empty(n_points, device="cuda")
+    times = {}
+    nfb = 0
+    for name in ("closed_form", "surrogate_thr_0p01_db", "surrogate_no_fallback"):
+        def run():
+            if name == "closed_form":
+                eng.closed_form_points(xb, yb)
+                return 0
+            return s.eval_points(xb, yb, 0.01 if "0p01" in name else float("inf"))
+        run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            k = run()
+        torch.cuda.synchronize()
+        times[name] = (time.perf_counter() - t0) / 3
+        if "0p01" in name:
+            nfb = k
+    flop_pt = 2 * (16 * 256 + 3 * 256 * 256 + 256) * members
+    t_sur = times["surrogate_no_fallback"]
+    s.close()
+    return {"workload": (f"{members}-member 16-256x4-1 SiLU ensemble, BF16 MFMA; trained on {train_rows} "
+                         f"closed-form samples (2000 Adam steps of 1024 per member); {n_points} query points "
+                         f"(100 x 100 GHz grid squares, 80-100 km spans, 17-23 dBm)"),
+            "train_s": t_train, "train_loss_ln2": [float(v) for v in loss], "held_out_8192": res,
+            "points_per_s": {k: n_points / v for k, v in times.items()},
+            "fallback_fraction_bench": nfb / n_points,
+            "speedup_vs_closed_form": times["closed_form"] / times["surrogate_thr_0p01_db"],
+            "mlp_tflops": flop_pt * n_points / t_sur / 1e12, "mlp_peak_bf16_tflops": 2500.0}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -137,6 +202,8 @@ def main():
                     help="links of the batched leg (0 = skip)")
     ap.add_argument("--plain-links", type=int, default=48,
                     help="links of the batch evaluated one by one on the plain path for comparison")
+    ap.add_argument("--surrogate-points", type=int, default=1 << 22,
+                    help="query points of the surrogate leg (0 = skip)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the steps, copy this many MiB device-to-device (counter calibration)")
     ap.add_argument("--traffic-bytes", type=float, default=None,
@@ -238,6 +305,9 @@ def main():
         out["fp64_value"] = n_cut / t64
     if args.batch_links > 0:
         out["batched"] = batched_leg(eng, args.batch_links, args.plain_links, W, torch)
+    if args.surrogate_points > 0:
+        log("surrogate leg")
+        out["surrogate"] = surrogate_leg(eng, args.surrogate_points, torch)
     eng.close()
 
     if args.calib_copy_mib:

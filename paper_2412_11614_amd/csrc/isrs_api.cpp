@@ -323,6 +323,7 @@ void plan_link_tables(const LinkInput& L, const isrs_numerics* nu, Plan& p)
         q.c3r = 2.0 * M_PI * M_PI * sp.beta3_ps3_km * dl;
         q.c2x = 4.0 * M_PI * M_PI * sp.beta2_ps2_km;
         q.c3x = 4.0 * M_PI * M_PI * M_PI * sp.beta3_ps3_km;
+        q.wd = 2.0 * M_PI / dl;
         q.p2r = 2.0 * M_PI * b2L;
         q.p3r = 2.0 * M_PI * M_PI * b3L;
         q.c2L = 2.0 * M_PI * sp.beta2_ps2_km * len;

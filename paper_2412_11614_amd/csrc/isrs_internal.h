@@ -14,7 +14,7 @@ constexpr int TILE = 32;
 constexpr int THREADS = 256;
 constexpr int PPT = 4;                // points per thread per tile
 constexpr int NAD = 2 * TILE - 1;     // anti-diagonals crossing a tile
-constexpr int STAGE_RUN = 16;         // anti-diagonals per staging run (one exp, then a recurrence)
+constexpr int STAGE_RUN = 8;          // anti-diagonals per staging run (one exp, then a recurrence)
 
 // Per-span constants, all FP64.  The phase of the segment step, Eq. 9, is
 // chi * Delta with chi of Eq. 24; the accumulated phase of Eq. 22 is Theta_s.
@@ -24,6 +24,7 @@ constexpr int STAGE_RUN = 16;         // anti-diagonals per staging run (one exp
 struct SpanConst {
     double c2r, c3r;       // 2 pi beta2 Delta,  2 pi^2 beta3 Delta
     double c2x, c3x;       // 4 pi^2 beta2,      4 pi^3 beta3
+    double wd;             // 2 pi / Delta: chi = wd * (chi Delta / 2 pi)
     double p2r, p3r;       // 2 pi sum_{s'<s} beta2 L,  2 pi^2 sum_{s'<s} beta3 L
     double c2L, c3L;       // 2 pi beta2 L,  2 pi^2 beta3 L  (Maclaurin form)
     double em;             // exp(-alpha Delta)

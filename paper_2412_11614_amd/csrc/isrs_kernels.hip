@@ -50,7 +50,7 @@ struct Prec<double> {
 
 __device__ __forceinline__ void sincos_rev(float t, float* s, float* c)
 {
-    // hardware sine / cosine take revolutions; |t| <= 1/2 here
+    // hardware sine / cosine take revolutions; 0 <= t < 1 here
     *s = __builtin_amdgcn_sinf(t);
     *c = __builtin_amdgcn_cosf(t);
 }
@@ -62,6 +62,45 @@ __device__ __forceinline__ void sincos_rev(double t, double* s, double* c)
 
 __device__ __forceinline__ float exp_r(float x) { return expf(x); }
 __device__ __forceinline__ double exp_r(double x) { return exp(x); }
+
+// exp(-zeta x): FP32 through the hardware base-2 exponential, FP64 exact
+__device__ __forceinline__ float exp_neg(float zeta, double x)
+{
+    return __builtin_amdgcn_exp2f(-zeta * 1.44269504088896341f * float(x));
+}
+__device__ __forceinline__ double exp_neg(double zeta, double x) { return exp(-zeta * x); }
+
+// 1 / x: FP32 hardware reciprocal (1 ulp), FP64 division
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
+// t - floor(t) of a phase in revolutions, then in the working precision
+template <typename R>
+__device__ __forceinline__ R frac_rev(double t)
+{
+    return R(__builtin_amdgcn_fract(t));
+}
+
+// segments 4 kq .. 4 kq + 3 of a staged row
+__device__ __forceinline__ void load4(const float4* row, int kq, float& g0, float& g1, float& g2, float& g3)
+{
+    const float4 v = row[kq];
+    g0 = v.x;
+    g1 = v.y;
+    g2 = v.z;
+    g3 = v.w;
+}
+__device__ __forceinline__ void load4(const double2* row, int kq, double& g0, double& g1, double& g2, double& g3)
+{
+    const double2 a = row[2 * kq], b = row[2 * kq + 1];
+    g0 = a.x;
+    g1 = a.y;
+    g2 = b.x;
+    g3 = b.y;
+}
+
+__device__ __forceinline__ float4 pack_vec(const float (&g)[4]) { return float4{g[0], g[1], g[2], g[3]}; }
+__device__ __forceinline__ double2 pack_vec(const double (&g)[2]) { return double2{g[0], g[1]}; }
 
 __device__ __forceinline__ double wave_sum(double v)
 {
@@ -96,8 +135,7 @@ __device__ void region_unit(const RegionArgs& a, const int u, VecOf<R>* g_vec, d
     using Vec = typename P::Vec;
     using Seg = typename P::Seg;
     constexpr int KC = P::KC, KP = P::KP, VW = P::VW, KPV = KP / VW;
-    // g rows of the tile's anti-diagonals; read as 16-byte vectors, written as scalars
-    R* const g_lds = reinterpret_cast<R*>(g_vec);
+    // g_vec: g rows of the tile's anti-diagonals, KPV vectors per row
 
     const int tid = threadIdx.x;
     const int item = u / a.n_groups;
@@ -152,56 +190,42 @@ __device__ void region_unit(const RegionArgs& a, const int u, VecOf<R>* g_vec, d
 
             const double f1 = (ip + 0.5 - 0.5 * N) * h;
             const double d1 = d1b + f1;
-            double d12[PPT], sab[PPT];
-            int mm[PPT];
-            bool ok[PPT];
+            // per point: pa = d12 = (f1 - f)(f2 - f) and pb = d12 (f1 + f2), FP64
+            double pa[PPT], pb[PPT];
             R ur[PPT], ui[PPT];  // Upsilon of each point
 #pragma unroll
             for (int r = 0; r < PPT; ++r) {
                 const int jr = j0 + lj + 8 * r;
                 const double f2 = (jr + 0.5 - 0.5 * N) * h;
-                ok[r] = ip < N && jr < N;
-                d12[r] = d1 * (d2b + f2);
-                sab[r] = sb + f1 + f2;
-                mm[r] = li + lj + 8 * r;
+                pa[r] = d1 * (d2b + f2);
+                pb[r] = pa[r] * (sb + f1 + f2);
                 ur[r] = R(0);
                 ui[r] = R(0);
             }
 
             for (int s = 0; s < lk.n_sp; ++s) {
                 const SpanConst sc = spans[s];
-                R qr[PPT], qi[PPT], i0r[PPT], i0i[PPT], rr[PPT], ri[PPT];
+                // rotation of the span's contribution: gamma Pi e^{i Theta_s} (Eq. 22)
+                R rr[PPT], ri[PPT];
 #pragma unroll
                 for (int r = 0; r < PPT; ++r) {
-                    // accumulated phase Theta_s of Eq. 22 and gain product
-                    double tt = d12[r] * (sc.p2r + sc.p3r * sab[r]);
-                    tt -= rint(tt);
                     R st, ct;
-                    sincos_rev(R(tt), &st, &ct);
+                    sincos_rev(frac_rev<R>(fma(pa[r], sc.p2r, pb[r] * sc.p3r)), &st, &ct);
                     R gm = R(sc.gamma);
-                    if (lk.gain_mode == 1) gm *= exp_r(R(sc.pi_a - sc.pi_s * sab[r] + sc.pi_c * cabs));
+                    if (lk.gain_mode == 1) {
+                        const double sab = sb + f1 + (j0 + lj + 8 * r + 0.5 - 0.5 * N) * h;
+                        gm *= exp_r(R(sc.pi_a - sc.pi_s * sab + sc.pi_c * cabs));
+                    }
                     rr[r] = gm * ct;
                     ri[r] = gm * st;
-                    const double chi = d12[r] * (sc.c2x + sc.c3x * sab[r]);
-                    const R al = R(sc.alpha), ch = R(chi);
-                    if constexpr (MU == 0) {
-                        double tq = d12[r] * (sc.c2r + sc.c3r * sab[r]);
-                        tq -= rint(tq);
-                        R sq, cq;
-                        sincos_rev(R(tq), &sq, &cq);
-                        qr[r] = R(sc.em) * cq;
-                        qi[r] = R(sc.em) * sq;
-                        // I_0 = (q - 1) / (i chi - alpha)
-                        const R vr = qr[r] - R(1), vi = qi[r];
-                        const R inv = R(1) / (al * al + ch * ch);
-                        i0r[r] = (-al * vr + ch * vi) * inv;
-                        i0i[r] = (-ch * vr - al * vi) * inv;
-                    } else {
-                        // Maclaurin form, Eqs. 4-6
-                        double tl = d12[r] * (sc.c2L + sc.c3L * sab[r]);
-                        tl -= rint(tl);
+                }
+                if constexpr (MU != 0) {
+                    // Maclaurin form, Eqs. 4-6
+#pragma unroll
+                    for (int r = 0; r < PPT; ++r) {
+                        const R al = R(sc.alpha), ch = R(fma(pa[r], sc.c2x, pb[r] * sc.c3x));
                         R sl, cl;
-                        sincos_rev(R(tl), &sl, &cl);
+                        sincos_rev(frac_rev<R>(fma(pa[r], sc.c2L, pb[r] * sc.c3L)), &sl, &cl);
                         const R inv1 = R(1) / (al * al + ch * ch);
                         const R inv2 = R(1) / (R(4) * al * al + ch * ch);
                         // eta = (e^{(i chi - a) L} - 1) / (i chi - a)
@@ -211,80 +235,103 @@ __device__ void region_unit(const RegionArgs& a, const int u, VecOf<R>* g_vec, d
                         vr = R(sc.em2L) * cl - R(1);
                         vi = R(sc.em2L) * sl;
                         const R fr = (R(-2) * al * vr + ch * vi) * inv2, fi = (-ch * vr - R(2) * al * vi) * inv2;
-                        const R x3 = R(sab[r] - cabs);
+                        const R x3 = R(sb + f1 + (j0 + lj + 8 * r + 0.5 - 0.5 * N) * h - cabs);
                         const R c = R(sc.pcr) * x3 / al;
                         const R mr = er - c * (er - fr), mi = ei - c * (ei - fi);
                         ur[r] += rr[r] * mr - ri[r] * mi;
                         ui[r] += rr[r] * mi + ri[r] * mr;
                     }
+                    continue;
                 }
-                if constexpr (MU != 0) continue;
 
+                // Segment form.  q = e^{(i chi - alpha) Delta}; the span's factor
+                // c = rotation * I_0 with I_0 = (q - 1) / (i chi - alpha).
+                R qr[PPT], qi[PPT], cr[PPT], ci[PPT], tq2[PPT];
+#pragma unroll
+                for (int r = 0; r < PPT; ++r) {
+                    const double tq = fma(pa[r], sc.c2r, pb[r] * sc.c3r);   // chi Delta / 2 pi
+                    R sq, cq;
+                    sincos_rev(frac_rev<R>(tq), &sq, &cq);
+                    const R al = R(sc.alpha), ch = R(tq) * R(sc.wd);
+                    qr[r] = R(sc.em) * cq;
+                    qi[r] = R(sc.em) * sq;
+                    const R vr = qr[r] - R(1), vi = qi[r];
+                    const R inv = recip(al * al + ch * ch);
+                    const R i0r = (-al * vr + ch * vi) * inv;
+                    const R i0i = (-ch * vr - al * vi) * inv;
+                    cr[r] = rr[r] * i0r - ri[r] * i0i;
+                    ci[r] = rr[r] * i0i + ri[r] * i0r;
+                    tq2[r] = R(2) * qr[r];
+                }
                 // Goertzel state per point; s = |q|^2 is uniform over the span
-                R b1[PPT], b2[PPT], tq2[PPT];
+                const R ms = R(-(sc.em * sc.em));
+                R b1[PPT], b2[PPT];
 #pragma unroll
                 for (int r = 0; r < PPT; ++r) {
                     b1[r] = R(0);
                     b2[r] = R(0);
-                    tq2[r] = R(2) * qr[r];
                 }
-                const R ms = R(-(sc.em * sc.em));
                 const int Kp4 = (sc.K + 3) & ~3;
                 for (int kc1 = Kp4; kc1 > 0; kc1 -= KC) {
                     const int kc0 = kc1 > KC ? kc1 - KC : 0;
                     const int len = kc1 - kc0;
-                    __syncthreads();  // previous readers of g_lds are done
+                    __syncthreads();  // previous readers of the staged rows are done
                     // stage g_k(f3) = A_k exp(-zeta_k f3abs) for the tile's anti-diagonals:
-                    // one exp per run of STAGE_RUN anti-diagonals, then the step ratio
-                    const int runs = (NAD + STAGE_RUN - 1) / STAGE_RUN;
-                    for (int t = tid; t < len * runs; t += THREADS) {
-                        const int kk = t % len, run = t / len, k = kc0 + kk;
-                        R gA = R(0), z = R(0), rt = R(0);
-                        if (k < sc.K) {
-                            const Seg row = seg[sc.off + k];
-                            gA = row.A;
-                            z = row.zeta;
-                            rt = row.ratio;
-                        }
-                        const double x = x3b + (mb + run * STAGE_RUN + 1 - N) * h;
-                        R g = (k < sc.K) ? gA * exp_r(-z * R(x)) : R(0);
+                    // an item is VW consecutive segments of a run of SRUN anti-diagonals,
+                    // one exp per segment at the run's first anti-diagonal, then the
+                    // step ratio exp(-zeta h) down the run, one vector write per row
+                    constexpr int SRUN = STAGE_RUN;
+                    constexpr int RUNS = (NAD + SRUN - 1) / SRUN;
+                    const int lenv = len / VW;
+                    for (int t = tid; t < lenv * RUNS; t += THREADS) {
+                        const int kv = t % lenv, run = t / lenv;
+                        const double x = x3b + (mb + run * SRUN + 1 - N) * h;
+                        R g[VW], rt[VW];
 #pragma unroll
-                        for (int q = 0; q < STAGE_RUN; ++q) {
-                            const int m = run * STAGE_RUN + q;
-                            if (m < NAD) g_lds[m * KP + kk] = g;
-                            g *= rt;
+                        for (int e = 0; e < VW; ++e) {
+                            const int k = kc0 + kv * VW + e;
+                            g[e] = R(0);
+                            rt[e] = R(0);
+                            if (k < sc.K) {
+                                const Seg row = seg[sc.off + k];
+                                g[e] = row.A * exp_neg(row.zeta, x);
+                                rt[e] = row.ratio;
+                            }
+                        }
+                        Vec* dst = g_vec + (run * SRUN) * KPV + kv;
+#pragma unroll
+                        for (int q = 0; q < SRUN; ++q) {
+                            if (run * SRUN + q < NAD) dst[q * KPV] = pack_vec(g);
+#pragma unroll
+                            for (int e = 0; e < VW; ++e) g[e] *= rt[e];
                         }
                     }
                     __syncthreads();
                     // every point reads its own anti-diagonal row: one base index
-                    // plus compile-time row offsets (8 rows apart per point)
+                    // plus compile-time row offsets (8 rows apart per point).  Four
+                    // segments per step: b2 takes b_k, then b1 takes b_{k-1}, so the
+                    // state never moves between registers.
                     const Vec* gb = g_vec + (li + lj) * KPV;
-                    // two segments per pair of updates: b2 takes b_k, then b1 takes
-                    // b_{k-1}, so the state never moves between registers
 #pragma unroll 2
-                    for (int kv = len / VW - 1; kv >= 0; --kv) {
-                        Vec v[PPT];
+                    for (int kq = len / 4 - 1; kq >= 0; --kq) {
+                        R g0[PPT], g1[PPT], g2[PPT], g3[PPT];
 #pragma unroll
-                        for (int r = 0; r < PPT; ++r) v[r] = gb[r * 8 * KPV + kv];
+                        for (int r = 0; r < PPT; ++r) load4(gb + r * 8 * KPV, kq, g0[r], g1[r], g2[r], g3[r]);
 #pragma unroll
                         for (int r = 0; r < PPT; ++r) {
-                            if constexpr (VW == 4) {
-                                b2[r] = fma(ms, b2[r], fma(tq2[r], b1[r], v[r].w));
-                                b1[r] = fma(ms, b1[r], fma(tq2[r], b2[r], v[r].z));
-                            }
-                            b2[r] = fma(ms, b2[r], fma(tq2[r], b1[r], v[r].y));
-                            b1[r] = fma(ms, b1[r], fma(tq2[r], b2[r], v[r].x));
+                            b2[r] = fma(ms, b2[r], fma(tq2[r], b1[r], g3[r]));
+                            b1[r] = fma(ms, b1[r], fma(tq2[r], b2[r], g2[r]));
+                            b2[r] = fma(ms, b2[r], fma(tq2[r], b1[r], g1[r]));
+                            b1[r] = fma(ms, b1[r], fma(tq2[r], b2[r], g0[r]));
                         }
                     }
                 }
 #pragma unroll
                 for (int r = 0; r < PPT; ++r) {
-                    // P(q) = b_0 - conj(q) b_1;  mu = I_0 P;  Upsilon += gamma Pi e^{i Theta} mu
+                    // P(q) = b_0 - conj(q) b_1;  Upsilon += c P
                     const R pr = b1[r] - qr[r] * b2[r], pi = qi[r] * b2[r];
-                    const R mr = i0r[r] * pr - i0i[r] * pi;
-                    const R mi = i0r[r] * pi + i0i[r] * pr;
-                    ur[r] += rr[r] * mr - ri[r] * mi;
-                    ui[r] += rr[r] * mi + ri[r] * mr;
+                    ur[r] += cr[r] * pr - ci[r] * pi;
+                    ui[r] += cr[r] * pi + ci[r] * pr;
                 }
             }
 
@@ -292,9 +339,9 @@ __device__ void region_unit(const RegionArgs& a, const int u, VecOf<R>* g_vec, d
             const double S1 = ip < N ? Sg[ip] : 0.0;
 #pragma unroll
             for (int r = 0; r < PPT; ++r) {
-                if (!ok[r]) continue;
                 const int jr = j0 + lj + 8 * r;
-                const int m = mb + mm[r];
+                if (ip >= N || jr >= N) continue;
+                const int m = mb + li + lj + 8 * r;
                 const double S2 = Sg[jr];
                 const double u2 = (double)ur[r] * (double)ur[r] + (double)ui[r] * (double)ui[r];
                 const double v = S1 * S1 * S2 * S2 * u2;
