@@ -24,12 +24,35 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 # The region kernel is bound by FP32 vector ALU issue.  Peak: the chip's FP32
-# vector rate, 256 CU x 4 SIMD x 16 lanes x 2 FLOP (FMA) x 2 (packed pair) x
-# 2.4 GHz = 157.3 TFLOP/s.  The build disables packed FP32 instructions, so
-# the attainable ceiling for this code is the non-packed FMA rate, half of it
-# (78.6 TFLOP/s, also the FP64 vector peak).
+# vector rate, 256 CU x 4 SIMD x 16 lanes x 2 FLOP (FMA) x 2 x 2.4 GHz =
+# 157.3 TFLOP/s.  gfx950 issues non-packed v_fma_f32 at up to ~1.9 wave
+# instructions per CU per clock (149 TFLOP/s measured on independent chains),
+# so this is also the ceiling for a build without packed FP32.
 PEAK_FP32_TFLOPS = 256 * 4 * 16 * 2 * 2 * 2.4e9 / 1e12
-PEAK_NONPACKED_TFLOPS = PEAK_FP32_TFLOPS / 2
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "region_kernel_traffic_cl100ch_10span_256.md")
+
+
+def measured_traffic():
+    """HBM bytes per region launch from the committed counter summary, or None
+    when the kernel source has changed since the counters were taken."""
+    import hashlib
+
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    fields = dict(line.split(": ", 1) for line in text.splitlines()
+                  if line.startswith(("traffic_bytes_per_launch: ", "kernel_source_sha256: ")))
+    csrc = os.path.join(ROOT, "paper_2412_11614_amd", "csrc")
+    h = hashlib.sha256()
+    for name in ("isrs_kernels.hip", "isrs_internal.h"):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(f.read())
+    if fields.get("kernel_source_sha256", "").strip() != h.hexdigest():
+        return None
+    return float(fields["traffic_bytes_per_launch"])
 
 
 def log(*a):
@@ -207,7 +230,7 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the steps, copy this many MiB device-to-device (counter calibration)")
     ap.add_argument("--traffic-bytes", type=float, default=None,
-                    help="HBM bytes per region launch measured with FETCH_SIZE/WRITE_SIZE (reported as-is)")
+                    help="override the HBM bytes per region launch (default: the committed counter summary)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the path is single-GPU "
@@ -279,11 +302,13 @@ def main():
                                 f"FP32 integrand / FP64 phase and sums"),
                    "n_cut": int(n_cut), "grid": args.grid, "spans": 10, "channels": 100},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": args.traffic_bytes,
+                     "frac": achieved / PEAK_FP32_TFLOPS,
+                     "traffic": args.traffic_bytes if args.traffic_bytes is not None else measured_traffic(),
                      "kernel": "region_kernel<float, 0>", "per_launch_ms": per_launch_ms,
                      "alg_flop_per_launch": st.alg_flop / st.region_launches,
-                     "peak_nonpacked_fma": PEAK_NONPACKED_TFLOPS,
-                     "frac_of_nonpacked": achieved / PEAK_NONPACKED_TFLOPS},
+                     # the Goertzel form executes 4 of the 8 algorithmic FLOP per segment
+                     "executed_fma_tflops": 4.0 * st.horner_steps / st.region_launches
+                     / (per_launch_ms * 1e-3) / 1e12},
         "detail": {"region_ms": st.region_ms, "egn_ms": st.egn_ms, "assemble_ms": st.assemble_ms,
                    "host_prep_ms": st.host_prep_ms, "squares": st.n_squares,
                    "delta_squares": st.n_delta_squares, "live_points": st.n_points_live,

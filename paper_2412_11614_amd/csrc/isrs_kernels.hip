@@ -310,7 +310,8 @@ __device__ void region_unit(const RegionArgs& a, const int u, VecOf<R>* g_vec, d
                     // every point reads its own anti-diagonal row: one base index
                     // plus compile-time row offsets (8 rows apart per point).  Four
                     // segments per step: b2 takes b_k, then b1 takes b_{k-1}, so the
-                    // state never moves between registers.
+                    // state never moves between registers; the older state enters the
+                    // inner product, so one FMA per segment is on the dependency chain.
                     const Vec* gb = g_vec + (li + lj) * KPV;
 #pragma unroll 2
                     for (int kq = len / 4 - 1; kq >= 0; --kq) {
@@ -319,10 +320,10 @@ __device__ void region_unit(const RegionArgs& a, const int u, VecOf<R>* g_vec, d
                         for (int r = 0; r < PPT; ++r) load4(gb + r * 8 * KPV, kq, g0[r], g1[r], g2[r], g3[r]);
 #pragma unroll
                         for (int r = 0; r < PPT; ++r) {
-                            b2[r] = fma(ms, b2[r], fma(tq2[r], b1[r], g3[r]));
-                            b1[r] = fma(ms, b1[r], fma(tq2[r], b2[r], g2[r]));
-                            b2[r] = fma(ms, b2[r], fma(tq2[r], b1[r], g1[r]));
-                            b1[r] = fma(ms, b1[r], fma(tq2[r], b2[r], g0[r]));
+                            b2[r] = fma(tq2[r], b1[r], fma(ms, b2[r], g3[r]));
+                            b1[r] = fma(tq2[r], b2[r], fma(ms, b1[r], g2[r]));
+                            b2[r] = fma(tq2[r], b1[r], fma(ms, b2[r], g1[r]));
+                            b1[r] = fma(tq2[r], b2[r], fma(ms, b1[r], g0[r]));
                         }
                     }
                 }
