@@ -285,11 +285,8 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
 // (FP64, then BF16): cos and sin of chi L and of chi Delta (the phases whose
 // ripple the closed form carries), ln(1 + |chi| / alpha) / 8 - 1, and
 // alpha / |beta|, chi / |beta| with beta = i chi - alpha.
-__global__ void features_kernel(int rows, const float* x, __bf16* xb)
+__device__ void features_row(const float* xi, float* f)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= rows) return;
-    const float* xi = x + (long)i * NIN;
     const Phys p = decode(xi);
     const double alpha = alpha_of(p), chi = chi_of(p);
     const int K = (int)ceil(p.L / 1.0);
@@ -297,7 +294,6 @@ __global__ void features_kernel(int rows, const float* x, __bf16* xb)
     sincos(chi * p.L, &sl, &cl);
     sincos(chi * (p.L / K), &sd, &cd);
     const double m = sqrt(alpha * alpha + chi * chi);
-    float f[NIN];
 #pragma unroll
     for (int j = 0; j < NF; ++j) f[j] = xi[j];
     f[9] = (float)cl;
@@ -307,8 +303,121 @@ __global__ void features_kernel(int rows, const float* x, __bf16* xb)
     f[13] = (float)(chi / m);
     f[14] = (float)cd;
     f[15] = (float)sd;
+}
+
+__global__ void features_kernel(int rows, const float* x, __bf16* xb)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows) return;
+    float f[NIN];
+    features_row(x + (long)i * NIN, f);
 #pragma unroll
     for (int j = 0; j < NIN; ++j) xb[(long)i * NIN + j] = (__bf16)f[j];
+}
+
+// Fused inference: a block takes FB_M query points through every member's
+// four hidden layers and output layer.  The activations of the tile stay in
+// LDS (BF16, rows padded to LDH so the 16-byte row reads of an MFMA operand
+// fall in distinct banks); weights stream from L2 as W^T rows.  Wave w owns
+// output columns 64 w .. 64 w + 63 of every layer: 4 x 2 tiles of 32 x 32.
+constexpr int FB_M = 128;
+constexpr int LDH = NH + 8;
+constexpr int LDX = NIN + 8;
+
+// acc[rt][ct] = rows 32 rt .. + 31 of src times W columns 64 w + 32 ct .. + 31,
+// over K (a compile-time count, fully unrolled so weight loads issue early).
+template <int K, int LD>
+__device__ __forceinline__ void fused_products(const __bf16* src, const __bf16* Wt, int w, int lr, int kh,
+                                               f16v (&acc)[4][2])
+{
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) {
+        acc[rt][0] = f16v{};
+        acc[rt][1] = f16v{};
+    }
+#pragma unroll
+    for (int ks = 0; ks < K / 16; ++ks) {
+        const int kk = 16 * ks + kh;
+        bf8 bv[2];
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) bv[ct] = *reinterpret_cast<const bf8*>(Wt + (size_t)(64 * w + 32 * ct + lr) * K + kk);
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) {
+            const bf8 av = *reinterpret_cast<const bf8*>(src + (32 * rt + lr) * LD + kk);
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct)
+                acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv[ct], acc[rt][ct], 0, 0, 0);
+        }
+    }
+}
+
+struct FusedArgs {
+    const float* x;
+    int64_t n;
+    int members;
+    float shift, scale;
+    float* pred;                        // [members][n]
+    const __bf16* wt[MAX_MEMBERS][4];   // W_l^T, [256][k_in]
+    const float* p[MAX_MEMBERS];        // FP32 parameters (biases, w5, b5)
+};
+
+__global__ void __launch_bounds__(256, 2) mlp_fused_kernel(FusedArgs a)
+{
+    __shared__ __attribute__((aligned(16))) __bf16 Hs[FB_M * LDH];
+    __shared__ __attribute__((aligned(16))) __bf16 Xs[FB_M * LDX];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t row0 = (int64_t)blockIdx.x * FB_M;
+    if (tid < FB_M) {
+        float f[NIN];
+        if (row0 + tid < a.n) {
+            features_row(a.x + (row0 + tid) * NIN, f);
+        } else {
+#pragma unroll
+            for (int j = 0; j < NIN; ++j) f[j] = 0.0f;
+        }
+#pragma unroll
+        for (int j = 0; j < NIN; ++j) Xs[tid * LDX + j] = (__bf16)f[j];
+    }
+    __syncthreads();
+    const int lr = lane & 31, kh = 8 * (lane >> 5);
+    for (int m = 0; m < a.members; ++m) {
+        const float* pm = a.p[m];
+        for (int l = 0; l < 4; ++l) {
+            const __bf16* src = l == 0 ? Xs : Hs;
+            const __bf16* Wt = a.wt[m][l];
+            f16v acc[4][2];
+            if (l == 0)
+                fused_products<NIN, LDX>(src, Wt, w, lr, kh, acc);
+            else
+                fused_products<NH, LDH>(src, Wt, w, lr, kh, acc);
+            __syncthreads();  // every wave has read the layer's input
+            const float* bias = pm + B_OFF[l];
+            const float bc[2] = {bias[64 * w + lr], bias[64 * w + 32 + lr]};
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+                for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const int row = 32 * rt + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                        const float z = acc[rt][ct][r] + bc[ct];
+                        Hs[row * LDH + 64 * w + 32 * ct + lr] = (__bf16)(z * sigm(z));
+                    }
+            __syncthreads();
+        }
+        // output layer: two threads per row, 128 columns each
+        {
+            const int rr = tid >> 1, half = tid & 1;
+            const float* w5 = pm + OFF_W5 + 128 * half;
+            const __bf16* h = Hs + rr * LDH + 128 * half;
+            float s = 0.0f;
+#pragma unroll 8
+            for (int c = 0; c < 128; ++c) s += (float)h[c] * w5[c];
+            s += __shfl_xor(s, 1, 64);
+            if (half == 0 && row0 + rr < a.n) a.pred[(int64_t)m * a.n + row0 + rr] = a.shift + a.scale * (s + pm[OFF_B5]);
+        }
+        __syncthreads();  // the tile's activations are free for the next member
+    }
 }
 
 // Output layer o = shift + scale (H4 w5 + b5), one wave per row.
@@ -773,18 +882,22 @@ int32_t ensure_pred(isrs_ctx* c, isrs_surrogate* s, int64_t n)
     return ISRS_OK;
 }
 
-constexpr int PRED_ROWS = 65536;  // rows per forward chunk
-
 int32_t predict_members(isrs_ctx* c, isrs_surrogate* s, const float* x, int64_t n, hipStream_t st)
 {
-    int32_t rc = ensure_batch(c, s, (int)std::min<int64_t>(PRED_ROWS, ((n + 63) / 64) * 64));
+    int32_t rc = ensure_pred(c, s, n);
     if (rc) return rc;
-    if ((rc = ensure_pred(c, s, n))) return rc;
-    for (int64_t r0 = 0; r0 < n; r0 += PRED_ROWS) {
-        const int rows = (int)std::min<int64_t>(PRED_ROWS, n - r0);
-        if ((rc = pack_rows(c, s, x, r0, rows, st))) return rc;
-        for (int mi = 0; mi < s->n_members; ++mi) forward(s, s->mem[mi], s->xb, rows, false, s->pred + mi * n + r0, true, st);
+    FusedArgs fa{};
+    fa.x = x;
+    fa.n = n;
+    fa.members = s->n_members;
+    fa.shift = (float)s->shift;
+    fa.scale = (float)s->scale;
+    fa.pred = s->pred;
+    for (int m = 0; m < s->n_members; ++m) {
+        for (int l = 0; l < 4; ++l) fa.wt[m][l] = s->mem[m].wt[l];
+        fa.p[m] = s->mem[m].p;
     }
+    hipLaunchKernelGGL(mlp_fused_kernel, dim3((unsigned)((n + FB_M - 1) / FB_M)), dim3(256), 0, st, fa);
     S_TRY(c, hipGetLastError());
     return ISRS_OK;
 }
