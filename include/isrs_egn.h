@@ -321,6 +321,20 @@ int32_t isrs_surrogate_set_params(isrs_ctx* ctx, isrs_surrogate* sur, int32_t me
 int32_t isrs_surrogate_grad(isrs_ctx* ctx, isrs_surrogate* sur, int32_t member, const float* x_dev,
                             const float* r_dev, int64_t n, float* grads, double* loss);
 
+/* eta (Eq. 11) of the context's link with the surrogate in the loop: for
+ * every grid point and span, |mu_s| comes from the ensemble and the phase
+ * from Eq. 6 (mu = eta_6 exp(r/2), r the predicted residual), coherently
+ * summed over spans as in Eq. 22.  Where the ensemble spread exceeds
+ * spread_db_threshold (dB of |mu|^2; < 0: everywhere), where a query lies
+ * outside the sampling box, or when B_tot is not 10 THz, the segment closed
+ * form (Eqs. 7-10) is used.  FP32 integrand, FP64 phases and sums; numerics
+ * and errors as isrs_eval_eta.  eta host [n_cut]; fallback_fraction (host,
+ * nullable) receives the share of live (point, span) pairs that took the
+ * closed form. */
+int32_t isrs_eval_eta_surrogate(isrs_ctx* ctx, isrs_surrogate* sur, const isrs_numerics* numerics,
+                                const int32_t* cuts, int32_t n_cut, double spread_db_threshold, double* eta,
+                                double* fallback_fraction);
+
 /* Checkpoint: weights, Adam moments, step counters and seed. */
 int32_t isrs_surrogate_save(isrs_surrogate* sur, const char* path);
 int32_t isrs_surrogate_load(isrs_ctx* ctx, isrs_surrogate* sur, const char* path);

@@ -39,6 +39,7 @@ EXPORTED = [
     "isrs_surrogate_predict", "isrs_surrogate_eval_points", "isrs_closed_form_points",
     "isrs_surrogate_num_params", "isrs_surrogate_get_params", "isrs_surrogate_set_params",
     "isrs_surrogate_grad", "isrs_surrogate_save", "isrs_surrogate_load", "isrs_surrogate_get_target_scale",
+    "isrs_eval_eta_surrogate",
 ]
 
 SUR_FEATURES = 16
@@ -145,6 +146,7 @@ def lib():
     L.isrs_surrogate_save.argtypes = [vp, C.c_char_p]
     L.isrs_surrogate_load.argtypes = [vp, vp, C.c_char_p]
     L.isrs_surrogate_get_target_scale.argtypes = [vp, dp, dp]
+    L.isrs_eval_eta_surrogate.argtypes = [vp, vp, C.POINTER(Numerics_c), ip, C.c_int32, C.c_double, dp, dp]
     for name in EXPORTED:
         f = getattr(L, name)
         if f.restype is C.c_int:  # default
@@ -380,6 +382,17 @@ class Surrogate:
                                                       _dev(x, "torch.float32", 16 * n),
                                                       _dev(r, "torch.float32", n), n, _fp(g), C.byref(loss)))
         return g, loss.value
+
+    def eval_eta(self, numerics, cuts, spread_db_threshold, **override):
+        """eta of the engine's loaded link with the surrogate in the loop;
+        returns (eta, fallback_fraction)."""
+        nu = numerics if isinstance(numerics, Numerics_c) else numerics_struct(numerics, **override)
+        cuts = np.ascontiguousarray(np.asarray(cuts, dtype=np.int32))
+        eta = np.zeros(len(cuts))
+        fb = C.c_double()
+        self._e._check(self._e._L.isrs_eval_eta_surrogate(self._e._h, self._h, C.byref(nu), _ip(cuts), len(cuts),
+                                                          float(spread_db_threshold), _dp(eta), C.byref(fb)))
+        return eta, fb.value
 
     def target_scale(self):
         """(shift, scale): the network's raw output predicts (r - shift) / scale."""

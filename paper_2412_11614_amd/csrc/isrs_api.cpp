@@ -136,14 +136,14 @@ struct Plan {
 // Device side of a plan.
 struct Workspace {
     DevBuf links, spans, seg, Sg, wt, s3, livep, insts, items, order, partD, partE, Y, dlist, counter, out,
-        power, phi, psi;
+        power, phi, psi, sur;
     HostBuf stage;
     hipEvent_t ev_upload = nullptr;
     std::vector<hipEvent_t> ev_pool;
     void release()
     {
         DevBuf* bufs[] = {&links, &spans, &seg, &Sg, &wt, &s3, &livep, &insts, &items, &order, &partD, &partE,
-                          &Y, &dlist, &counter, &out, &power, &phi, &psi};
+                          &Y, &dlist, &counter, &out, &power, &phi, &psi, &sur};
         for (DevBuf* b : bufs) b->release();
         stage.release();
         if (ev_upload) (void)hipEventDestroy(ev_upload);
@@ -324,6 +324,10 @@ void plan_link_tables(const LinkInput& L, const isrs_numerics* nu, Plan& p)
         q.c2x = 4.0 * M_PI * M_PI * sp.beta2_ps2_km;
         q.c3x = 4.0 * M_PI * M_PI * M_PI * sp.beta3_ps3_km;
         q.wd = 2.0 * M_PI / dl;
+        q.L = len;
+        q.cr = sp.cr_w_km_thz;
+        q.ptot = ptot;
+        q.btot = B;
         q.p2r = 2.0 * M_PI * b2L;
         q.p3r = 2.0 * M_PI * M_PI * b3L;
         q.c2L = 2.0 * M_PI * sp.beta2_ps2_km * len;
@@ -491,7 +495,7 @@ void plan_link_work(const LinkInput& L, int link, const isrs_numerics* nu, const
 }
 
 // Launch chunks (bounded coherent-sum buffer), strip grouping and queue order.
-void plan_finish(Plan& p, size_t ycap, const Tuning& tu)
+void plan_finish(Plan& p, size_t ycap, const Tuning& tu, int max_items = 0)
 {
     p.seg32.resize(p.seg64.size());
     for (size_t i = 0; i < p.seg64.size(); ++i)
@@ -506,6 +510,11 @@ void plan_finish(Plan& p, size_t ycap, const Tuning& tu)
         SquareItem& it = p.items[i];
         it.y_slot = -1;
         it.d_index = -1;
+        if (max_items > 0 && (int)i - p.chunk_begin.back() == max_items) {
+            p.chunk_begin.push_back((int)i);
+            p.dchunk_begin.push_back((int)p.dlist.size());
+            slots = 0;
+        }
         if (it.egn_mask == 0) continue;
         if (slots == per_chunk) {
             p.chunk_begin.push_back((int)i);
@@ -655,7 +664,8 @@ struct Timings {
 
 // Stream-ordered launches of a plan (graph-capturable when timing is off).
 int32_t plan_enqueue(isrs_ctx* c, Workspace& w, const Plan& p, const Tuning& tu, hipStream_t st, double* eta_d,
-                     double* s2_d, double* terms_d, double* psd_d, bool assemble, Timings* tm)
+                     double* s2_d, double* terms_d, double* psd_d, bool assemble, Timings* tm,
+                     SurrogateFill* sf = nullptr, float* sur_tab = nullptr)
 {
     RegionArgs ra{};
     ra.links = w.links.as<LinkDesc>();
@@ -716,6 +726,11 @@ int32_t plan_enqueue(isrs_ctx* c, Workspace& w, const Plan& p, const Tuning& tu,
         if (tu.mode == 1) {
             ra.counter = w.counter.as<int>() + ch;
             HIP_TRY(c, launch_zero_counter(ra.counter, st));
+        }
+        if (sf) {
+            ra.sur_tab = sur_tab;
+            ra.sur_item0 = b;
+            if ((rc = sf->fill(c, ra, b, e, p.links[0].n_sp, sur_tab, st))) return rc;
         }
         if ((rc = mark(ev_reg, true))) return rc;
         HIP_TRY(c, launch_region(ra, blocks, p.fp32, st));
@@ -806,7 +821,7 @@ LinkInput ctx_link(const isrs_ctx* c, const int32_t* cuts, int n_cut)
 // pointers; partials_host receives island partials in explicit-square mode.
 int32_t evaluate(isrs_ctx* c, const isrs_numerics* nu, const int32_t* cuts, int n_cut, const int32_t* kappa12,
                  int m_explicit, double* eta_d, double* s2_d, double* terms_d, double* psd_d,
-                 double* partials_host)
+                 double* partials_host, SurrogateFill* sf = nullptr)
 {
     auto t0 = std::chrono::steady_clock::now();
     if (!c) return ISRS_E_ARG;
@@ -822,13 +837,22 @@ int32_t evaluate(isrs_ctx* c, const isrs_numerics* nu, const int32_t* cuts, int 
             if (kappa12[t] < 0 || kappa12[t] >= c->n_ch) return fail(c, ISRS_E_ARG, "square index out of range");
     }
     HIP_TRY(c, hipSetDevice(c->device));
+    // the surrogate path: FP32 integrand, residual table with segment fallback
+    isrs_numerics nn = *nu;
+    int max_items = 0;
+    if (sf) {
+        nn.precision = ISRS_PREC_FP32_PHASE64;
+        nn.mu_method = 2;
+        const int64_t rows_per_item = (int64_t)nu->n1 * nu->n1 * (int64_t)c->spans.size();
+        max_items = (int)std::max<int64_t>(1, SUR_TAB_ROWS / std::max<int64_t>(1, rows_per_item));
+    }
     Plan p;
     Tuning tu;
     try {
-        plan_begin(nu, p);
-        plan_link_tables(L, nu, p);
-        plan_link_work(L, 0, nu, kappa12, m_explicit, p);
-        plan_finish(p, c->ycap, tu);
+        plan_begin(&nn, p);
+        plan_link_tables(L, &nn, p);
+        plan_link_work(L, 0, &nn, kappa12, m_explicit, p);
+        plan_finish(p, c->ycap, tu, max_items);
         plan_queue_shape(c, tu, p);
     } catch (const std::bad_alloc&) {
         return fail(c, ISRS_E_NOMEM, "host allocation failed");
@@ -836,10 +860,11 @@ int32_t evaluate(isrs_ctx* c, const isrs_numerics* nu, const int32_t* cuts, int 
     Workspace& w = *c->ws;
     int32_t rc;
     if ((rc = plan_upload(c, w, p, c->stream))) return rc;
+    if (sf) HIP_TRY(c, w.sur.ensure((size_t)max_items * p.N * p.N * p.links[0].n_sp * sizeof(float)));
     auto t1 = std::chrono::steady_clock::now();
     Timings tm;
     if ((rc = plan_enqueue(c, w, p, tu, c->stream, eta_d, s2_d, terms_d, psd_d, partials_host == nullptr,
-                           c->profiling ? &tm : nullptr)))
+                           c->profiling ? &tm : nullptr, sf, sf ? w.sur.as<float>() : nullptr)))
         return rc;
     if (partials_host) {
         std::vector<double> pd(p.items.size() * p.n_groups * 3), pe(std::max<size_t>(1, p.dlist.size()) * 12);
@@ -1054,6 +1079,28 @@ hipStream_t ctx_stream(isrs_ctx* c) { return c->stream; }
 int ctx_device(const isrs_ctx* c) { return c->device; }
 int ctx_num_cu(const isrs_ctx* c) { return c->n_cu; }
 int32_t ctx_fail(isrs_ctx* c, int32_t code, const char* msg) { return fail(c, code, msg); }
+
+int32_t eval_eta_table(isrs_ctx* c, const isrs_numerics* nu, const int32_t* cuts, int n_cut, SurrogateFill& sf,
+                       double* eta_host)
+{
+    if (!c) return ISRS_E_ARG;
+    if (!eta_host) return fail(c, ISRS_E_ARG, "eta output is null");
+    if (n_cut < 1) return fail(c, ISRS_E_ARG, "need at least one CUT");
+    HIP_TRY(c, hipSetDevice(c->device));
+    const size_t n = (size_t)n_cut;
+    HIP_TRY(c, c->ws->out.ensure(n * 7 * sizeof(double)));
+    double* d = c->ws->out.as<double>();
+    int32_t rc = evaluate(c, nu, cuts, n_cut, nullptr, 0, d, d + n, d + 2 * n, nullptr, nullptr, &sf);
+    if (rc) return rc;
+    std::vector<double> h(n);
+    HIP_TRY(c, hipMemcpyAsync(h.data(), d, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (size_t q = 0; q < n; ++q) {
+        if (!is_fin(h[q])) return fail(c, ISRS_E_NUMERIC, "non-finite NLI result");
+        eta_host[q] = h[q];
+    }
+    return ISRS_OK;
+}
 }  // namespace isrs
 
 extern "C" {

@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/isrs_egn.h"
+
 namespace isrs {
 
 // Region tile: TILE x TILE grid points per pass, 256 threads, each thread
@@ -25,6 +27,7 @@ struct SpanConst {
     double c2r, c3r;       // 2 pi beta2 Delta,  2 pi^2 beta3 Delta
     double c2x, c3x;       // 4 pi^2 beta2,      4 pi^3 beta3
     double wd;             // 2 pi / Delta: chi = wd * (chi Delta / 2 pi)
+    double L, cr, ptot, btot;  // length (km), Cr, total power (W) and bandwidth (THz) of Eq. 25
     double p2r, p3r;       // 2 pi sum_{s'<s} beta2 L,  2 pi^2 sum_{s'<s} beta3 L
     double c2L, c3L;       // 2 pi beta2 L,  2 pi^2 beta3 L  (Maclaurin form)
     double em;             // exp(-alpha Delta)
@@ -104,7 +107,9 @@ struct RegionArgs {
     int spb;                  // tile strips per group
     int nt;                   // tiles per side
     int N;
-    int mu_method;
+    int mu_method;            // 0 segment form, 1 Maclaurin form, 2 surrogate table with segment fallback
+    const float* sur_tab;     // mu_method 2: ln(|mu|^2 / |eta_6|^2) per (point, span), NaN = closed form;
+    int sur_item0;            //   row ((item - sur_item0) * N + j) * N + i) * n_sp + s
 };
 
 struct EgnArgs {
@@ -149,10 +154,21 @@ int region_blocks_per_cu(bool fp32, int mu_method);
 }  // namespace isrs
 
 // Context accessors for the surrogate's host code (isrs_surrogate.hip).
-struct isrs_ctx;
 namespace isrs {
 hipStream_t ctx_stream(isrs_ctx* c);
 int ctx_device(const isrs_ctx* c);
 int ctx_num_cu(const isrs_ctx* c);
 int32_t ctx_fail(isrs_ctx* c, int32_t code, const char* msg);
+
+// Evaluation of the context's link with the region kernel reading a residual
+// table (mu_method 2): before each launch chunk, fill() writes the table rows
+// of squares [item0, item1) and counts live and fallback rows.
+struct SurrogateFill {
+    virtual ~SurrogateFill() = default;
+    virtual int32_t fill(isrs_ctx* c, const RegionArgs& ra, int item0, int item1, int n_sp, float* tab,
+                         hipStream_t st) = 0;
+};
+constexpr int64_t SUR_TAB_ROWS = int64_t(1) << 25;  // table rows per launch chunk
+int32_t eval_eta_table(isrs_ctx* c, const isrs_numerics* nu, const int32_t* cuts, int n_cut, SurrogateFill& sf,
+                       double* eta_host);
 }  // namespace isrs

@@ -219,7 +219,7 @@ __device__ void region_unit(const RegionArgs& a, const int u, VecOf<R>* g_vec, d
                     rr[r] = gm * ct;
                     ri[r] = gm * st;
                 }
-                if constexpr (MU != 0) {
+                if constexpr (MU == 1) {
                     // Maclaurin form, Eqs. 4-6
 #pragma unroll
                     for (int r = 0; r < PPT; ++r) {
@@ -242,6 +242,37 @@ __device__ void region_unit(const RegionArgs& a, const int u, VecOf<R>* g_vec, d
                         ui[r] += rr[r] * mi + ri[r] * mr;
                     }
                     continue;
+                }
+
+                // Surrogate table (MU 2): mu = eta_6 e^{r / 2} with eta_6 of Eq. 6 (its
+                // phase kept), r the ensemble's residual; NaN rows take the segment
+                // form below, which then runs for the whole block.
+                bool fb[PPT];
+#pragma unroll
+                for (int r = 0; r < PPT; ++r) fb[r] = MU == 0;
+                if constexpr (MU == 2) {
+                    bool any = false;
+#pragma unroll
+                    for (int r = 0; r < PPT; ++r) {
+                        const int jr = j0 + lj + 8 * r;
+                        float rv = 0.0f;
+                        if (ip < N && jr < N)
+                            rv = a.sur_tab[(((size_t)(item - a.sur_item0) * N + jr) * N + ip) * lk.n_sp + s];
+                        fb[r] = rv != rv;
+                        any |= fb[r];
+                        if (fb[r]) continue;
+                        const double tq = fma(pa[r], sc.c2r, pb[r] * sc.c3r);   // chi Delta / 2 pi
+                        const R al = R(sc.alpha), ch = R(tq) * R(sc.wd);
+                        R sl, cl;
+                        sincos_rev(frac_rev<R>(fma(pa[r], sc.c2L, pb[r] * sc.c3L)), &sl, &cl);
+                        const R vr = R(sc.emL) * cl - R(1), vi = R(sc.emL) * sl;
+                        const R inv = recip(al * al + ch * ch);
+                        const R g = exp_r(R(0.5) * R(rv));
+                        const R mr = (-al * vr + ch * vi) * inv * g, mi = (-ch * vr - al * vi) * inv * g;
+                        ur[r] += rr[r] * mr - ri[r] * mi;
+                        ui[r] += rr[r] * mi + ri[r] * mr;
+                    }
+                    if (!__syncthreads_or(any)) continue;
                 }
 
                 // Segment form.  q = e^{(i chi - alpha) Delta}; the span's factor
@@ -330,6 +361,7 @@ __device__ void region_unit(const RegionArgs& a, const int u, VecOf<R>* g_vec, d
 #pragma unroll
                 for (int r = 0; r < PPT; ++r) {
                     // P(q) = b_0 - conj(q) b_1;  Upsilon += c P
+                    if (!fb[r]) continue;
                     const R pr = b1[r] - qr[r] * b2[r], pi = qi[r] * b2[r];
                     ur[r] += cr[r] * pr - ci[r] * pi;
                     ui[r] += cr[r] * pi + ci[r] * pr;
@@ -364,12 +396,13 @@ __device__ void region_unit(const RegionArgs& a, const int u, VecOf<R>* g_vec, d
     }
 }
 
-// FP32: at most 168 VGPRs, three waves per SIMD
-template <typename R>
-constexpr int region_min_waves() { return sizeof(R) == 4 ? 3 : 2; }
+// FP32: at most 168 VGPRs, three waves per SIMD; the surrogate-table variant
+// keeps both code paths live and takes two.
+template <typename R, int MU>
+constexpr int region_min_waves() { return sizeof(R) == 4 && MU != 2 ? 3 : 2; }
 
 template <typename R, int MU>
-__global__ void __launch_bounds__(THREADS, region_min_waves<R>()) region_kernel(RegionArgs a)
+__global__ void __launch_bounds__(THREADS, (region_min_waves<R, MU>())) region_kernel(RegionArgs a)
 {
     __shared__ VecOf<R> g_vec[NAD * (Prec<R>::KP / Prec<R>::VW)];
     __shared__ double red[THREADS / 64];
@@ -379,7 +412,7 @@ __global__ void __launch_bounds__(THREADS, region_min_waves<R>()) region_kernel(
 // Persistent blocks on a queue: every block pops unit positions until the
 // launch's units are exhausted, so every block reaches the exit.
 template <typename R, int MU>
-__global__ void __launch_bounds__(THREADS, region_min_waves<R>()) region_queue_kernel(RegionArgs a)
+__global__ void __launch_bounds__(THREADS, (region_min_waves<R, MU>())) region_queue_kernel(RegionArgs a)
 {
     __shared__ VecOf<R> g_vec[NAD * (Prec<R>::KP / Prec<R>::VW)];
     __shared__ double red[THREADS / 64];
@@ -621,6 +654,10 @@ hipError_t launch_region_t(const RegionArgs& a, int blocks, hipStream_t st)
 hipError_t launch_region(const RegionArgs& a, int blocks, bool fp32, hipStream_t st)
 {
     if (a.n_units == 0) return hipSuccess;
+    if (a.mu_method == 2) {
+        if (!fp32 || !a.sur_tab) return hipErrorInvalidValue;   // the table path runs the FP32 integrand
+        return launch_region_t<float, 2>(a, blocks, st);
+    }
     if (fp32)
         return a.mu_method == 0 ? launch_region_t<float, 0>(a, blocks, st) : launch_region_t<float, 1>(a, blocks, st);
     return a.mu_method == 0 ? launch_region_t<double, 0>(a, blocks, st) : launch_region_t<double, 1>(a, blocks, st);
@@ -637,7 +674,9 @@ int region_blocks_per_cu(bool fp32, int mu_method)
 {
     int n = 0;
     hipError_t e;
-    if (fp32)
+    if (mu_method == 2)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, region_queue_kernel<float, 2>, THREADS, 0);
+    else if (fp32)
         e = mu_method == 0 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, region_queue_kernel<float, 0>, THREADS, 0)
                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, region_queue_kernel<float, 1>, THREADS, 0);
     else

@@ -612,6 +612,100 @@ __global__ void fallback_kernel(const int* total, const int64_t* idx, const floa
     y[i] = (float)yy;
 }
 
+// Query rows of squares [item0, item0 + rows / (N^2 n_sp)) of a plan, one per
+// (grid point, span): row ((item - item0) N + j) N + i) n_sp + s, i the f1
+// index and j the f2 index of the square.  state: 0 no live island at the
+// point, 1 a query inside the sampling box, 2 outside it (closed form).
+__global__ void sur_query_kernel(RegionArgs ra, int item0, int64_t rows, int n_sp, float* x, unsigned char* state)
+{
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= rows) return;
+    const int N = ra.N, AD = 2 * N - 1;
+    const int s = (int)(row % n_sp);
+    int64_t t = row / n_sp;
+    const int i = (int)(t % N);
+    t /= N;
+    const int j = (int)(t % N);
+    const int item = item0 + (int)(t / N);
+    const SquareItem it = ra.items[item];
+    const InstDesc in = ra.insts[it.inst];
+    const LinkDesc lk = ra.links[in.link];
+    const SpanConst sc = ra.spans[lk.span0 + s];
+    const double* wt = ra.wt + lk.tab0 + (size_t)in.nf_idx * 3 * AD;
+    bool live = false;
+    for (int l = 0; l < 3; ++l)
+        if (((it.lmask >> l) & 1) && wt[l * AD + i + j] != 0.0) live = true;
+    float* xr = x + row * NIN;
+    if (!live) {
+        state[row] = 0;
+        for (int q = 0; q < NIN; ++q) xr[q] = 0.0f;
+        return;
+    }
+    const double hg = 0.5 * (lk.n_ch - 1), df = lk.spacing, h = lk.h;
+    double ph[NF];
+    ph[0] = (it.k1 - hg) * df + (i + 0.5 - 0.5 * N) * h;
+    ph[1] = (it.k2 - hg) * df + (j + 0.5 - 0.5 * N) * h;
+    ph[2] = (in.cut - hg) * df + in.f;
+    ph[3] = sc.L;
+    ph[4] = sc.alpha * (10.0 / M_LN10);
+    ph[5] = sc.c2x / (4.0 * M_PI * M_PI);
+    ph[6] = sc.c3x / (4.0 * M_PI * M_PI * M_PI);
+    ph[7] = sc.cr;
+    ph[8] = 10.0 * log10(sc.ptot / 1e-3);
+    bool inbox = fabs(sc.btot - 10.0) <= 1e-9;
+    for (int q = 0; q < NF; ++q) {
+        const double v = 2.0 * (ph[q] - c_lo[q]) / (c_hi[q] - c_lo[q]) - 1.0;
+        if (!(fabs(v) <= 1.0 + 1e-9)) inbox = false;
+        xr[q] = (float)fmin(1.0, fmax(-1.0, v));
+    }
+    for (int q = NF; q < NIN; ++q) xr[q] = 0.0f;
+    state[row] = inbox ? 1 : 2;
+}
+
+// Table rows from the ensemble: 0 where no island is live, NaN (closed form)
+// outside the box or where the spread exceeds thr_ln (thr_ln < 0: everywhere),
+// else the ensemble mean.  Per-block counts of live and fallback rows.
+__global__ void sur_combine_kernel(int64_t rows, int members, const float* pred, const unsigned char* state,
+                                   double thr_ln, float* tab, int* cnt_live, int* cnt_fb)
+{
+    __shared__ int sl[4], sf[4];
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int live = 0, fbk = 0;
+    if (row < rows) {
+        const unsigned char st = state[row];
+        float v = 0.0f;
+        if (st != 0) {
+            live = 1;
+            if (st == 2 || thr_ln < 0.0) {
+                fbk = 1;
+            } else {
+                float sum = 0.0f, lo = 3.4e38f, hi = -3.4e38f;
+                for (int m = 0; m < members; ++m) {
+                    const float p = pred[(int64_t)m * rows + row];
+                    sum += p;
+                    lo = fminf(lo, p);
+                    hi = fmaxf(hi, p);
+                }
+                if ((double)(hi - lo) > thr_ln) fbk = 1;
+                else v = sum / members;
+            }
+            if (fbk) v = __builtin_nanf("");
+        }
+        tab[row] = v;
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nl = __popcll(__ballot(live)), nf = __popcll(__ballot(fbk));
+    if (lane == 0) {
+        sl[w] = nl;
+        sf[w] = nf;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        cnt_live[blockIdx.x] = sl[0] + sl[1] + sl[2] + sl[3];
+        cnt_fb[blockIdx.x] = sf[0] + sf[1] + sf[2] + sf[3];
+    }
+}
+
 unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
@@ -660,6 +754,11 @@ struct isrs_surrogate {
     int* total = nullptr;
     int64_t* idx = nullptr;
     int64_t fcap = 0;
+    // query rows of the table path
+    float* qx = nullptr;
+    unsigned char* qstate = nullptr;
+    int* qcnt = nullptr;              // [2][blocks]
+    int64_t qcap = 0;
 };
 
 namespace {
@@ -992,6 +1091,9 @@ int32_t isrs_surrogate_destroy(isrs_surrogate* s)
     dfree(s->off);
     dfree(s->total);
     dfree(s->idx);
+    dfree(s->qx);
+    dfree(s->qstate);
+    dfree(s->qcnt);
     delete s;
     return ISRS_OK;
 }
@@ -1235,6 +1337,61 @@ int32_t isrs_surrogate_load(isrs_ctx* c, isrs_surrogate* s, const char* path)
     s->shift = sc[0];
     s->scale = sc[1];
     S_TRY(c, hipStreamSynchronize(st));
+    return ISRS_OK;
+}
+
+int32_t isrs_eval_eta_surrogate(isrs_ctx* c, isrs_surrogate* s, const isrs_numerics* nu, const int32_t* cuts,
+                                int32_t n_cut, double thr_db, double* eta, double* fallback_fraction)
+{
+    if (!c) return ISRS_E_ARG;
+    if (!s || !nu || !cuts || !eta) return ctx_fail(c, ISRS_E_ARG, "null argument");
+    if (std::isnan(thr_db)) return ctx_fail(c, ISRS_E_ARG, "threshold is NaN");
+    S_TRY(c, hipSetDevice(s->device));
+    struct Fill : SurrogateFill {
+        isrs_surrogate* s;
+        double thr_ln;
+        int64_t live = 0, fb = 0;
+        int32_t fill(isrs_ctx* c, const RegionArgs& ra, int item0, int item1, int n_sp, float* tab,
+                     hipStream_t st) override
+        {
+            const int64_t rows = (int64_t)(item1 - item0) * ra.N * ra.N * n_sp;
+            if (rows == 0) return ISRS_OK;
+            const unsigned nb = blocks_for(rows, 256);
+            if (rows > s->qcap) {
+                dfree(s->qx);
+                dfree(s->qstate);
+                dfree(s->qcnt);
+                s->qx = nullptr;
+                s->qstate = nullptr;
+                s->qcnt = nullptr;
+                s->qcap = 0;
+                S_TRY(c, dalloc(&s->qx, (size_t)rows * NIN));
+                S_TRY(c, dalloc(&s->qstate, (size_t)rows));
+                S_TRY(c, dalloc(&s->qcnt, 2 * (size_t)nb));
+                s->qcap = rows;
+            }
+            hipLaunchKernelGGL(sur_query_kernel, dim3(nb), dim3(256), 0, st, ra, item0, rows, n_sp, s->qx, s->qstate);
+            S_TRY(c, hipGetLastError());
+            int32_t rc = predict_members(c, s, s->qx, rows, st);
+            if (rc) return rc;
+            hipLaunchKernelGGL(sur_combine_kernel, dim3(nb), dim3(256), 0, st, rows, s->n_members, s->pred,
+                               s->qstate, thr_ln, tab, s->qcnt, s->qcnt + nb);
+            S_TRY(c, hipGetLastError());
+            std::vector<int> h(2 * (size_t)nb);
+            S_TRY(c, hipMemcpyAsync(h.data(), s->qcnt, h.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+            S_TRY(c, hipStreamSynchronize(st));
+            for (unsigned b = 0; b < nb; ++b) {
+                live += h[b];
+                fb += h[nb + b];
+            }
+            return ISRS_OK;
+        }
+    } f;
+    f.s = s;
+    f.thr_ln = thr_db < 0 ? -1.0 : thr_db / (10.0 / std::log(10.0));
+    int32_t rc = eval_eta_table(c, nu, cuts, n_cut, f, eta);
+    if (rc) return rc;
+    if (fallback_fraction) *fallback_fraction = f.live > 0 ? (double)f.fb / (double)f.live : 0.0;
     return ISRS_OK;
 }
 

@@ -219,3 +219,41 @@ def test_parameter_roundtrip_and_validation(engine, data):
     with pytest.raises(_lib.IsrsError):
         engine.surrogate(n_members=0)
     s.close()
+
+
+def test_eta_with_surrogate_all_fallback_equals_closed_form(engine):
+    """Threshold < 0: every (point, span) takes the segment form, through the
+    table variant of the region kernel: the same eta as the plain path."""
+    from paper_2412_11614_amd import workloads as W
+    wl = W.small_mixed(seed=31, n_ch=5, n_spans=2, n_grid=24)
+    engine.load(wl)
+    ref = engine.eval_eta(wl.numerics, wl.cuts, precision=W.PREC_FP32_PHASE64)["eta"]
+    s = engine.surrogate(n_members=2, seed=3)
+    for thr in (-1.0, float("inf")):     # this link is outside the sampling box: always the closed form
+        eta, fb = s.eval_eta(wl.numerics, wl.cuts, thr)
+        assert fb == 1.0
+        assert np.allclose(eta, ref, rtol=1e-6, atol=0), (thr, eta, ref)
+    s.close()
+
+
+def test_eta_with_surrogate_in_box(engine, data):
+    """A link inside the sampling box (100 x 100 GHz grid, B_tot 10 THz): no
+    fallback at an infinite threshold, partial fallback at 0.01 dB, and eta
+    close to the closed form."""
+    from paper_2412_11614_amd import workloads as W
+    x, r, _ = data
+    s = engine.surrogate(n_members=4, seed=12)
+    s.train(x, r, steps=800, batch=1024, lr=1e-3)
+    wl = W.cl_100ch_10span(n_grid=16)
+    cuts = np.array([3, 50, 96], dtype=np.int32)
+    engine.load(wl)
+    ref = engine.eval_eta(wl.numerics, cuts, precision=W.PREC_FP32_PHASE64)["eta"]
+    eta_inf, fb_inf = s.eval_eta(wl.numerics, cuts, float("inf"))
+    eta_01, fb_01 = s.eval_eta(wl.numerics, cuts, 0.01)
+    err_inf = 10 * np.log10(eta_inf / ref)
+    err_01 = 10 * np.log10(eta_01 / ref)
+    print("surrogate eta error dB", err_inf, "fallback", fb_inf, "| thr 0.01:", err_01, fb_01, flush=True)
+    assert fb_inf == 0.0 and 0.0 < fb_01 < 1.0
+    assert np.max(np.abs(err_inf)) < 0.5
+    assert np.max(np.abs(err_01)) <= np.max(np.abs(err_inf)) + 1e-3
+    s.close()
