@@ -147,6 +147,26 @@ def batched_leg(eng, n_links, n_plain, W, torch):
             "max_abs_db_batch_vs_plain": agree}
 
 
+def per_cut_dz_leg(eng, wl, eta_dz1, W, torch):
+    """The segment form's step chosen per CUT (error model on a 32 x 32 grid,
+    0.005 dB against a 0.5 km step), then the full workload with those steps."""
+    cuts = wl.cuts
+    cand = [0.5, 1.0, 2.0, 3.0, 4.0, 5.0, 6.0, 7.0]
+    eng.load(wl)
+    t0 = time.perf_counter()
+    dz, _ = eng.choose_dz(wl.numerics, cuts, cand, 0.005, precision=W.PREC_FP64, n=32)
+    t_choose = time.perf_counter() - t0
+    r = eng.eval_eta_dz(wl.numerics, cuts, dz, precision=W.PREC_FP32_PHASE64)      # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = eng.eval_eta_dz(wl.numerics, cuts, dz, precision=W.PREC_FP32_PHASE64)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"choose_s": t_choose, "dz_km_min": float(dz.min()), "dz_km_max": float(dz.max()),
+            "dz_km_mean": float(dz.mean()), "value": len(cuts) / dt, "unit": "CUT/s",
+            "max_abs_db_vs_dz1": float(np.max(np.abs(10 * np.log10(r["eta"] / eta_dz1))))}
+
+
 def surrogate_leg(eng, n_points, torch, train_rows=1 << 20, members=4):
     """Ensemble surrogate of the per-span FWM factor: training time, held-out
     error against the closed form, and throughput of inference with fallback
@@ -201,6 +221,23 @@ def surrogate_leg(eng, n_points, torch, train_rows=1 << 20, members=4):
             nfb = k
     flop_pt = 2 * (16 * 256 + 3 * 256 * 256 + 256) * members
     t_sur = times["surrogate_no_fallback"]
+    # surrogate in the loop: eta of 3 CUTs of the C+L link at 64^2
+    from paper_2412_11614_amd import workloads as W
+    wl = W.cl_100ch_10span(n_grid=64)
+    cuts = np.array([3, 50, 96], dtype=np.int32)
+    eng.load(wl)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ref = eng.eval_eta(wl.numerics, cuts, precision=W.PREC_FP32_PHASE64)["eta"]
+    t_cf = time.perf_counter() - t0
+    loop = {"workload": "C+L link (100 x 96 GBd, 10 spans), CUTs 3/50/96, 64x64 per square",
+            "closed_form_s": t_cf}
+    for name, thr in (("no_fallback", float("inf")), ("thr_0p01_db", 0.01)):
+        t0 = time.perf_counter()
+        eta, fb = s.eval_eta(wl.numerics, cuts, thr)
+        dt = time.perf_counter() - t0
+        loop[name] = {"s": dt, "fallback_fraction": fb,
+                      "eta_err_db": [float(v) for v in 10 * np.log10(eta / ref)]}
     s.close()
     return {"workload": (f"{members}-member 16-256x4-1 SiLU ensemble, BF16 MFMA; trained on {train_rows} "
                          f"closed-form samples (2000 Adam steps of 1024 per member); {n_points} query points "
@@ -209,7 +246,8 @@ def surrogate_leg(eng, n_points, torch, train_rows=1 << 20, members=4):
             "points_per_s": {k: n_points / v for k, v in times.items()},
             "fallback_fraction_bench": nfb / n_points,
             "speedup_vs_closed_form": times["closed_form"] / times["surrogate_thr_0p01_db"],
-            "mlp_tflops": flop_pt * n_points / t_sur / 1e12, "mlp_peak_bf16_tflops": 2500.0}
+            "mlp_tflops": flop_pt * n_points / t_sur / 1e12, "mlp_peak_bf16_tflops": 2500.0,
+            "eta_in_the_loop": loop}
 
 
 def main():
@@ -225,6 +263,7 @@ def main():
                     help="links of the batched leg (0 = skip)")
     ap.add_argument("--plain-links", type=int, default=48,
                     help="links of the batch evaluated one by one on the plain path for comparison")
+    ap.add_argument("--per-cut-dz", type=int, default=1, help="run the per-CUT step leg (0 = skip)")
     ap.add_argument("--surrogate-points", type=int, default=1 << 22,
                     help="query points of the surrogate leg (0 = skip)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -328,6 +367,8 @@ def main():
         out["accuracy"] = {"fp32_vs_fp64_max_abs_db": float(err.max()), "fp32_vs_fp64_mean_abs_db": float(err.mean()),
                            "within_0p01_db": bool(err.max() <= 0.01)}
         out["fp64_value"] = n_cut / t64
+    if args.per_cut_dz:
+        out["per_cut_dz"] = per_cut_dz_leg(eng, wl, eta32, W, torch)
     if args.batch_links > 0:
         out["batched"] = batched_leg(eng, args.batch_links, args.plain_links, W, torch)
     if args.surrogate_points > 0:

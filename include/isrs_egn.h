@@ -156,6 +156,22 @@ int32_t isrs_eval_eta(isrs_ctx* ctx, const isrs_numerics* numerics, const int32_
 int32_t isrs_eval_eta_dev(isrs_ctx* ctx, const isrs_numerics* numerics, const int32_t* cuts, int32_t n_cut,
                           double* eta_dev, double* sigma2_dev, double* terms_dev);
 
+/* eta with a sampling step per CUT: dz_km[q] replaces numerics->dz_km for
+ * cuts[q] (Sec. III-D: the segment form's step can follow the COI's
+ * frequency).  CUTs sharing a step share segment tables.  Outputs, units and
+ * errors as isrs_eval_eta; a bad step names its CUT (ISRS_E_ARG). */
+int32_t isrs_eval_eta_dz(isrs_ctx* ctx, const isrs_numerics* numerics, const int32_t* cuts, int32_t n_cut,
+                         const double* dz_km, double* eta, double* sigma2, double* terms);
+
+/* Error-model step choice: eta of every CUT at each candidate step (on the
+ * given numerics, normally a coarse grid) against the smallest candidate;
+ * dz_out[q] (host) receives the largest candidate whose |error| is within
+ * target_db (the smallest candidate if none is).  err_db_out (host,
+ * nullable, [n_cand][n_cut], candidates ascending) receives the errors. */
+int32_t isrs_choose_dz(isrs_ctx* ctx, const isrs_numerics* numerics, const int32_t* cuts, int32_t n_cut,
+                       const double* candidates, int32_t n_cand, double target_db, double* dz_out,
+                       double* err_db_out);
+
 /* NLI PSD at the n_f outer samples of each CUT (Eq. 15 without the outer
  * integral over f): f_thz host [n_cut*n_f] offsets from the CUT centre,
  * psd host [n_cut*n_f] in W/THz.  sigma^2 = sum_f (Rs/n_f) psd. */

@@ -39,7 +39,7 @@ EXPORTED = [
     "isrs_surrogate_predict", "isrs_surrogate_eval_points", "isrs_closed_form_points",
     "isrs_surrogate_num_params", "isrs_surrogate_get_params", "isrs_surrogate_set_params",
     "isrs_surrogate_grad", "isrs_surrogate_save", "isrs_surrogate_load", "isrs_surrogate_get_target_scale",
-    "isrs_eval_eta_surrogate",
+    "isrs_eval_eta_surrogate", "isrs_eval_eta_dz", "isrs_choose_dz",
 ]
 
 SUR_FEATURES = 16
@@ -146,6 +146,8 @@ def lib():
     L.isrs_surrogate_save.argtypes = [vp, C.c_char_p]
     L.isrs_surrogate_load.argtypes = [vp, vp, C.c_char_p]
     L.isrs_surrogate_get_target_scale.argtypes = [vp, dp, dp]
+    L.isrs_eval_eta_dz.argtypes = [vp, C.POINTER(Numerics_c), ip, C.c_int32, dp, dp, dp, dp]
+    L.isrs_choose_dz.argtypes = [vp, C.POINTER(Numerics_c), ip, C.c_int32, dp, C.c_int32, C.c_double, dp, dp]
     L.isrs_eval_eta_surrogate.argtypes = [vp, vp, C.POINTER(Numerics_c), ip, C.c_int32, C.c_double, dp, dp]
     for name in EXPORTED:
         f = getattr(L, name)
@@ -492,6 +494,30 @@ class Engine:
         terms = np.zeros((n, 5))
         self._check(self._L.isrs_eval_eta(self._h, C.byref(nu), _ip(cuts), n, _dp(eta), _dp(s2), _dp(terms)))
         return {"eta": eta, "sigma2": s2, "terms": terms}
+
+    def eval_eta_dz(self, numerics, cuts, dz_km, **override):
+        """eta with a sampling step per CUT (dz_km[q] for cuts[q])."""
+        nu = numerics if isinstance(numerics, Numerics_c) else numerics_struct(numerics, **override)
+        cuts = np.ascontiguousarray(np.asarray(cuts, dtype=np.int32))
+        dz = np.ascontiguousarray(np.asarray(dz_km, dtype=np.float64))
+        if dz.shape != cuts.shape:
+            raise ValueError("one step per CUT")
+        n = len(cuts)
+        eta, s2, terms = np.zeros(n), np.zeros(n), np.zeros((n, 5))
+        self._check(self._L.isrs_eval_eta_dz(self._h, C.byref(nu), _ip(cuts), n, _dp(dz), _dp(eta), _dp(s2),
+                                             _dp(terms)))
+        return {"eta": eta, "sigma2": s2, "terms": terms}
+
+    def choose_dz(self, numerics, cuts, candidates, target_db, **override):
+        """Per-CUT step from the error model; returns (dz [n_cut], err_db [n_cand, n_cut])."""
+        nu = numerics if isinstance(numerics, Numerics_c) else numerics_struct(numerics, **override)
+        cuts = np.ascontiguousarray(np.asarray(cuts, dtype=np.int32))
+        cand = np.ascontiguousarray(np.asarray(candidates, dtype=np.float64))
+        dz = np.zeros(len(cuts))
+        err = np.zeros((len(cand), len(cuts)))
+        self._check(self._L.isrs_choose_dz(self._h, C.byref(nu), _ip(cuts), len(cuts), _dp(cand), len(cand),
+                                           float(target_db), _dp(dz), _dp(err)))
+        return dz, err
 
     def eval_eta_dev(self, numerics, cuts, eta_dev, sigma2_dev=None, terms_dev=None, **override):
         """Device outputs (torch tensors of float64 on the context's GPU); stream-ordered."""

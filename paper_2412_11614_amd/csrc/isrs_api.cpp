@@ -819,9 +819,13 @@ LinkInput ctx_link(const isrs_ctx* c, const int32_t* cuts, int n_cut)
 
 // Single-link evaluation on the context's workspace.  Outputs are device
 // pointers; partials_host receives island partials in explicit-square mode.
+// dz_per_cut (nullable): a sampling step per CUT; CUTs sharing a step form one
+// link entry of the plan, so the outputs come in plan order, returned in
+// plan_order (plan position -> input index).
 int32_t evaluate(isrs_ctx* c, const isrs_numerics* nu, const int32_t* cuts, int n_cut, const int32_t* kappa12,
                  int m_explicit, double* eta_d, double* s2_d, double* terms_d, double* psd_d,
-                 double* partials_host, SurrogateFill* sf = nullptr)
+                 double* partials_host, SurrogateFill* sf = nullptr, const double* dz_per_cut = nullptr,
+                 std::vector<int>* plan_order = nullptr)
 {
     auto t0 = std::chrono::steady_clock::now();
     if (!c) return ISRS_E_ARG;
@@ -832,6 +836,35 @@ int32_t evaluate(isrs_ctx* c, const isrs_numerics* nu, const int32_t* cuts, int 
     LinkInput L = ctx_link(c, cuts, n_cut);
     m = validate_link_numerics(L, nu);
     if (!m.empty()) return fail(c, ISRS_E_ARG, m);
+    // groups of CUTs by sampling step
+    std::vector<double> gdz;
+    std::vector<std::vector<int32_t>> gcuts;
+    std::vector<int> order;
+    if (dz_per_cut) {
+        std::vector<int> idx(n_cut);
+        std::iota(idx.begin(), idx.end(), 0);
+        for (int q = 0; q < n_cut; ++q) {
+            isrs_numerics t = *nu;
+            t.dz_km = dz_per_cut[q];
+            m = validate_numerics_msg(&t);
+            if (m.empty()) m = validate_link_numerics(ctx_link(c, cuts + q, 1), &t);
+            if (!m.empty()) return fail(c, ISRS_E_ARG, "CUT " + std::to_string(q) + ": " + m);
+        }
+        std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return dz_per_cut[a] < dz_per_cut[b]; });
+        for (int q : idx) {
+            if (gdz.empty() || dz_per_cut[q] != gdz.back()) {
+                gdz.push_back(dz_per_cut[q]);
+                gcuts.emplace_back();
+            }
+            gcuts.back().push_back(cuts[q]);
+            order.push_back(q);
+        }
+    } else {
+        gdz.push_back(nu->dz_km);
+        gcuts.emplace_back(cuts, cuts + n_cut);
+        for (int q = 0; q < n_cut; ++q) order.push_back(q);
+    }
+    if (plan_order) *plan_order = order;
     if (kappa12) {
         for (int t = 0; t < 2 * m_explicit; ++t)
             if (kappa12[t] < 0 || kappa12[t] >= c->n_ch) return fail(c, ISRS_E_ARG, "square index out of range");
@@ -850,8 +883,15 @@ int32_t evaluate(isrs_ctx* c, const isrs_numerics* nu, const int32_t* cuts, int 
     Tuning tu;
     try {
         plan_begin(&nn, p);
-        plan_link_tables(L, &nn, p);
-        plan_link_work(L, 0, &nn, kappa12, m_explicit, p);
+        for (size_t g = 0; g < gdz.size(); ++g) {
+            isrs_numerics ng = nn;
+            ng.dz_km = gdz[g];
+            LinkInput Lg = L;
+            Lg.cuts = gcuts[g].data();
+            Lg.n_cut = (int)gcuts[g].size();
+            plan_link_tables(Lg, &ng, p);
+            plan_link_work(Lg, (int)g, &ng, kappa12, m_explicit, p);
+        }
         plan_finish(p, c->ycap, tu, max_items);
         plan_queue_shape(c, tu, p);
     } catch (const std::bad_alloc&) {
@@ -1284,6 +1324,68 @@ int32_t isrs_eval_eta(isrs_ctx* c, const isrs_numerics* nu, const int32_t* cuts,
         if (sigma2) sigma2[q] = h[n + q];
         if (terms)
             for (int u = 0; u < 5; ++u) terms[q * 5 + u] = h[2 * n + q * 5 + u];
+    }
+    return ISRS_OK;
+}
+
+int32_t isrs_eval_eta_dz(isrs_ctx* c, const isrs_numerics* nu, const int32_t* cuts, int32_t n_cut,
+                         const double* dz_km, double* eta, double* sigma2, double* terms)
+{
+    if (!c) return ISRS_E_ARG;
+    if (!eta || !dz_km) return fail(c, ISRS_E_ARG, "eta output or step array is null");
+    if (n_cut < 1) return fail(c, ISRS_E_ARG, "need at least one CUT");
+    HIP_TRY(c, hipSetDevice(c->device));
+    const size_t n = (size_t)n_cut;
+    HIP_TRY(c, c->ws->out.ensure(n * 7 * sizeof(double)));
+    double* d = c->ws->out.as<double>();
+    std::vector<int> order;
+    int32_t rc = evaluate(c, nu, cuts, n_cut, nullptr, 0, d, d + n, d + 2 * n, nullptr, nullptr, nullptr, dz_km, &order);
+    if (rc) return rc;
+    std::vector<double> h(n * 7);
+    HIP_TRY(c, hipMemcpyAsync(h.data(), d, n * 7 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (size_t pos = 0; pos < n; ++pos) {
+        const size_t q = (size_t)order[pos];
+        if (!is_fin(h[pos]) || !is_fin(h[n + pos])) return fail(c, ISRS_E_NUMERIC, "non-finite NLI result");
+        eta[q] = h[pos];
+        if (sigma2) sigma2[q] = h[n + pos];
+        if (terms)
+            for (int u = 0; u < 5; ++u) terms[q * 5 + u] = h[2 * n + pos * 5 + u];
+    }
+    return ISRS_OK;
+}
+
+int32_t isrs_choose_dz(isrs_ctx* c, const isrs_numerics* nu, const int32_t* cuts, int32_t n_cut,
+                       const double* candidates, int32_t n_cand, double target_db, double* dz_out,
+                       double* err_db_out)
+{
+    if (!c) return ISRS_E_ARG;
+    if (!nu || !cuts || !candidates || !dz_out || n_cut < 1 || n_cand < 1)
+        return fail(c, ISRS_E_ARG, "null argument or empty candidate / CUT list");
+    if (!(is_fin(target_db) && target_db >= 0)) return fail(c, ISRS_E_ARG, "target must be finite and >= 0");
+    std::vector<double> cand(candidates, candidates + n_cand);
+    for (double v : cand)
+        if (!(is_fin(v) && v > 0)) return fail(c, ISRS_E_ARG, "candidate steps must be finite and > 0");
+    std::sort(cand.begin(), cand.end());
+    const size_t n = (size_t)n_cut;
+    std::vector<double> ref(n), cur(n);
+    isrs_numerics t = *nu;
+    t.dz_km = cand[0];
+    int32_t rc = isrs_eval_eta(c, &t, cuts, n_cut, ref.data(), nullptr, nullptr);
+    if (rc) return rc;
+    for (size_t q = 0; q < n; ++q) dz_out[q] = cand[0];
+    for (int i = 0; i < n_cand; ++i) {
+        if (i > 0) {
+            t.dz_km = cand[i];
+            if ((rc = isrs_eval_eta(c, &t, cuts, n_cut, cur.data(), nullptr, nullptr))) return rc;
+        } else {
+            cur = ref;
+        }
+        for (size_t q = 0; q < n; ++q) {
+            const double e = 10.0 * std::log10(cur[q] / ref[q]);
+            if (err_db_out) err_db_out[(size_t)i * n + q] = e;
+            if (std::fabs(e) <= target_db) dz_out[q] = std::max(dz_out[q], cand[i]);
+        }
     }
     return ISRS_OK;
 }
