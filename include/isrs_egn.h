@@ -65,6 +65,10 @@ extern "C" {
 /* FWM efficiency factor per span. */
 #define ISRS_MU_SEGMENT 0   /* segment closed form, Eqs. 7-10 */
 #define ISRS_MU_MACLAURIN 1 /* Maclaurin closed form, Eqs. 2-6 */
+#define ISRS_MU_INTEGRAL 2  /* integral form, Eq. 23: on each of the K = ceil(L / dz) segments the
+                             * SRS gain is interpolated at 4 Gauss-Legendre nodes and the product
+                             * with exp((i chi - alpha) z) integrated exactly (error O(dz^4) for any
+                             * chi); the reference the closed forms approximate */
 
 typedef struct isrs_ctx isrs_ctx;
 

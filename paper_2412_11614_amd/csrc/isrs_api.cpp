@@ -252,7 +252,8 @@ std::string validate_numerics_msg(const isrs_numerics* nu)
     if (!(is_fin(nu->dz_km) && nu->dz_km > 0)) return "dz must be finite and > 0";
     if (nu->egn != 0 && nu->egn != 1) return "egn must be 0 or 1";
     if (nu->precision != ISRS_PREC_FP64 && nu->precision != ISRS_PREC_FP32_PHASE64) return "unknown precision";
-    if (nu->mu_method != ISRS_MU_SEGMENT && nu->mu_method != ISRS_MU_MACLAURIN) return "unknown mu method";
+    if (nu->mu_method != ISRS_MU_SEGMENT && nu->mu_method != ISRS_MU_MACLAURIN && nu->mu_method != ISRS_MU_INTEGRAL)
+        return "unknown mu method";
     return "";
 }
 
@@ -342,14 +343,16 @@ void plan_link_tables(const LinkInput& L, const isrs_numerics* nu, Plan& p)
         q.off = (int)p.seg64.size();
         b2L += sp.beta2_ps2_km * len;
         b3L += sp.beta3_ps3_km * len;
-        for (int k = 0; k < K; ++k) {
-            const double z = (k + 0.5) / K * len;
-            const double leff = -std::expm1(-alpha * z) / alpha;
-            const double X = B * ptot * sp.cr_w_km_thz * leff;
-            const double A = X == 0.0 ? 1.0 : X / (2.0 * std::sinh(0.5 * X));
-            const double zeta = X / B;
-            p.seg64.push_back({A, zeta, std::exp(-zeta * h), 0.0});
-        }
+        const int nodes = p.mu_method == MU_INT ? INT_NODES : 1;
+        for (int n = 0; n < nodes; ++n)
+            for (int k = 0; k < K; ++k) {
+                const double z = (k + 0.5 + (nodes > 1 ? 0.5 * INT_U[n] : 0.0)) / K * len;
+                const double leff = -std::expm1(-alpha * z) / alpha;
+                const double X = B * ptot * sp.cr_w_km_thz * leff;
+                const double A = X == 0.0 ? 1.0 : X / (2.0 * std::sinh(0.5 * X));
+                const double zeta = X / B;
+                p.seg64.push_back({A, zeta, std::exp(-zeta * h), 0.0});
+            }
         const double leffL = -std::expm1(-alpha * len) / alpha;
         const double XL = B * ptot * sp.cr_w_km_thz * leffL;
         lnA[s] = XL == 0.0 ? 0.0 : std::log(XL / (2.0 * std::sinh(0.5 * XL)));
@@ -571,7 +574,8 @@ int32_t upload(isrs_ctx* c, hipStream_t st, DevBuf& d, const std::vector<T>& v, 
 std::string plan_check(const Plan& p)
 {
     size_t rows = 0;
-    for (const SpanConst& q : p.spans) rows = std::max<size_t>(rows, (size_t)q.off + q.K);
+    const size_t nodes = p.mu_method == MU_INT ? INT_NODES : 1;
+    for (const SpanConst& q : p.spans) rows = std::max<size_t>(rows, (size_t)q.off + nodes * q.K);
     if ((p.fp32 ? p.seg32.size() : p.seg64.size()) < rows) return "segment table shorter than the spans need";
     const size_t AD = p.AD;
     for (const LinkDesc& d : p.links) {
@@ -875,7 +879,7 @@ int32_t evaluate(isrs_ctx* c, const isrs_numerics* nu, const int32_t* cuts, int 
     int max_items = 0;
     if (sf) {
         nn.precision = ISRS_PREC_FP32_PHASE64;
-        nn.mu_method = 2;
+        nn.mu_method = MU_SUR;
         const int64_t rows_per_item = (int64_t)nu->n1 * nu->n1 * (int64_t)c->spans.size();
         max_items = (int)std::max<int64_t>(1, SUR_TAB_ROWS / std::max<int64_t>(1, rows_per_item));
     }

@@ -18,6 +18,17 @@ constexpr int PPT = 4;                // points per thread per tile
 constexpr int NAD = 2 * TILE - 1;     // anti-diagonals crossing a tile
 constexpr int STAGE_RUN = 8;          // anti-diagonals per staging run (one exp, then a recurrence)
 
+// Forms of the per-span FWM factor run by the region kernel.
+constexpr int MU_SEG = 0;             // segment closed form, Eqs. 7-10
+constexpr int MU_MAC = 1;             // Maclaurin closed form, Eqs. 2-6
+constexpr int MU_INT = 2;             // integral form, Eq. 23, by 4-node product integration per segment
+constexpr int MU_SUR = 3;             // surrogate residual table with segment fallback (internal)
+constexpr int INT_NODES = 4;
+// Gauss-Legendre nodes on [-1, 1] at which the integral form samples the gain
+// inside each segment (node n of segment k at z = (k + 1/2 + u_n / 2) Delta).
+constexpr double INT_U[INT_NODES] = {-0.86113631159405258, -0.33998104358485626, 0.33998104358485626,
+                                     0.86113631159405258};
+
 // Per-span constants, all FP64.  The phase of the segment step, Eq. 9, is
 // chi * Delta with chi of Eq. 24; the accumulated phase of Eq. 22 is Theta_s.
 // Both are formed in revolutions from d12 = (f1-f)(f2-f) and s = f1 + f2:
@@ -42,7 +53,8 @@ struct SpanConst {
 
 // Segment table row k of a span: SRS gain at z_k = A exp(-zeta f3abs)
 // (Eq. 8 with Eq. 10) and the step ratio exp(-zeta h) between neighbouring
-// anti-diagonals of the grid.
+// anti-diagonals of the grid.  The integral form keeps INT_NODES such tables
+// per span (rows off + n K + k), sampled at the nodes inside each segment.
 struct SegRow64 {
     double A, zeta, ratio, pad;
 };
@@ -107,8 +119,8 @@ struct RegionArgs {
     int spb;                  // tile strips per group
     int nt;                   // tiles per side
     int N;
-    int mu_method;            // 0 segment form, 1 Maclaurin form, 2 surrogate table with segment fallback
-    const float* sur_tab;     // mu_method 2: ln(|mu|^2 / |eta_6|^2) per (point, span), NaN = closed form;
+    int mu_method;            // MU_SEG, MU_MAC, MU_INT or MU_SUR
+    const float* sur_tab;     // MU_SUR: ln(|mu|^2 / |eta_6|^2) per (point, span), NaN = closed form;
     int sur_item0;            //   row ((item - sur_item0) * N + j) * N + i) * n_sp + s
 };
 

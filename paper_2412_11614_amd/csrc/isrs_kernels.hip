@@ -126,6 +126,77 @@ __device__ double block_sum(double v, double* sh)
 template <typename R>
 using VecOf = typename Prec<R>::Vec;
 
+// m_j = int_{-1}^{1} u^j e^{a u} du, j = 0..3, for a = (ar, ai), e^{a} = (er, ei).
+// Power series for |a| < 1; otherwise m_0 = (e^a - e^{-a}) / a and the
+// integration-by-parts step m_j = (e^a - (-1)^j e^{-a}) / a - (j / a) m_{j-1}.
+template <typename R>
+__device__ __forceinline__ void node_moments(R ar, R ai, R er, R ei, R (&mr)[4], R (&mi)[4])
+{
+    const R a2 = ar * ar + ai * ai;
+    if (a2 < R(1)) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            mr[j] = R(0);
+            mi[j] = R(0);
+        }
+        R tr = R(1), ti = R(0);   // a^n / n!
+        constexpr int TERMS = sizeof(R) == 8 ? 22 : 12;
+#pragma unroll
+        for (int n = 0; n < TERMS; ++n) {
+            if (n > 0) {
+                const R inv_n = R(1) / R(n);
+                const R nr = (tr * ar - ti * ai) * inv_n;
+                ti = (tr * ai + ti * ar) * inv_n;
+                tr = nr;
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (((j + n) & 1) == 0) {
+                    const R w = R(2) / R(j + n + 1);
+                    mr[j] += w * tr;
+                    mi[j] += w * ti;
+                }
+        }
+        return;
+    }
+    // 1 / a and e^{-a} = conj(e^a) / |e^a|^2
+    const R ir = ar / a2, ii = -ai / a2;
+    const R e2 = er * er + ei * ei;
+    const R fr = er / e2, fi = -ei / e2;
+    R pr = R(0), pim = R(0);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const R sgn = (j & 1) ? R(-1) : R(1);
+        // (e^a - (-1)^j e^{-a} - j m_{j-1}) / a
+        const R nr = er - sgn * fr - R(j) * pr, ni = ei - sgn * fi - R(j) * pim;
+        mr[j] = nr * ir - ni * ii;
+        mi[j] = nr * ii + ni * ir;
+        pr = mr[j];
+        pim = mi[j];
+    }
+}
+
+// W_n = sum_j L[n][j] m_j with l_n(u) = sum_j L[n][j] u^j the Lagrange basis of
+// the four Gauss-Legendre nodes (monomial coefficients of the inverse Vandermonde).
+__constant__ double c_lag[INT_NODES][4] = {
+    {-0.092326598440728888, 0.10721484763524003, 0.79876206302836739, -0.92756750850486841},
+    {0.59232659844072888, -1.7422341910450931, -0.79876206302836739, 2.3494311759443818},
+    {0.59232659844072888, 1.7422341910450931, -0.79876206302836739, -2.3494311759443818},
+    {-0.092326598440728888, -0.10721484763524003, 0.79876206302836739, 0.92756750850486841}};
+
+template <typename R>
+__device__ __forceinline__ void node_weight(int n, const R (&mr)[4], const R (&mi)[4], R& wr, R& wi)
+{
+    wr = R(0);
+    wi = R(0);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const R c = R(c_lag[n][j]);
+        wr += c * mr[j];
+        wi += c * mi[j];
+    }
+}
+
 // One work unit: strip group u % n_groups of square u / n_groups.
 template <typename R, int MU>
 __device__ void region_unit(const RegionArgs& a, const int u, VecOf<R>* g_vec, double* red)
@@ -219,7 +290,7 @@ __device__ void region_unit(const RegionArgs& a, const int u, VecOf<R>* g_vec, d
                     rr[r] = gm * ct;
                     ri[r] = gm * st;
                 }
-                if constexpr (MU == 1) {
+                if constexpr (MU == MU_MAC) {
                     // Maclaurin form, Eqs. 4-6
 #pragma unroll
                     for (int r = 0; r < PPT; ++r) {
@@ -244,13 +315,13 @@ __device__ void region_unit(const RegionArgs& a, const int u, VecOf<R>* g_vec, d
                     continue;
                 }
 
-                // Surrogate table (MU 2): mu = eta_6 e^{r / 2} with eta_6 of Eq. 6 (its
+                // Surrogate table (MU_SUR): mu = eta_6 e^{r / 2} with eta_6 of Eq. 6 (its
                 // phase kept), r the ensemble's residual; NaN rows take the segment
                 // form below, which then runs for the whole block.
                 bool fb[PPT];
 #pragma unroll
-                for (int r = 0; r < PPT; ++r) fb[r] = MU == 0;
-                if constexpr (MU == 2) {
+                for (int r = 0; r < PPT; ++r) fb[r] = MU != MU_SUR;
+                if constexpr (MU == MU_SUR) {
                     bool any = false;
 #pragma unroll
                     for (int r = 0; r < PPT; ++r) {
@@ -275,9 +346,16 @@ __device__ void region_unit(const RegionArgs& a, const int u, VecOf<R>* g_vec, d
                     if (!__syncthreads_or(any)) continue;
                 }
 
-                // Segment form.  q = e^{(i chi - alpha) Delta}; the span's factor
-                // c = rotation * I_0 with I_0 = (q - 1) / (i chi - alpha).
+                // q = e^{(i chi - alpha) Delta}.  Segment form: the span's factor
+                // c = rotation * I_0 with I_0 = (q - 1) / (i chi - alpha) multiplies
+                // P(q) = sum_k g_k q^k.  Integral form: node n of every segment gives
+                // P_n(q) = sum_k g(z_kn) q^k, weighted by
+                // W_n = e^{a} (Delta / 2) int_{-1}^{1} l_n(u) e^{a u} du, a = (i chi - alpha) Delta / 2,
+                // l_n the Lagrange basis of the nodes (exact product integration of the
+                // interpolated gain against the exponential); c = rotation.
+                constexpr int NN = MU == MU_INT ? INT_NODES : 1;
                 R qr[PPT], qi[PPT], cr[PPT], ci[PPT], tq2[PPT];
+                R mre[MU == MU_INT ? PPT : 1][4], mim[MU == MU_INT ? PPT : 1][4];
 #pragma unroll
                 for (int r = 0; r < PPT; ++r) {
                     const double tq = fma(pa[r], sc.c2r, pb[r] * sc.c3r);   // chi Delta / 2 pi
@@ -286,85 +364,115 @@ __device__ void region_unit(const RegionArgs& a, const int u, VecOf<R>* g_vec, d
                     const R al = R(sc.alpha), ch = R(tq) * R(sc.wd);
                     qr[r] = R(sc.em) * cq;
                     qi[r] = R(sc.em) * sq;
-                    const R vr = qr[r] - R(1), vi = qi[r];
-                    const R inv = recip(al * al + ch * ch);
-                    const R i0r = (-al * vr + ch * vi) * inv;
-                    const R i0i = (-ch * vr - al * vi) * inv;
-                    cr[r] = rr[r] * i0r - ri[r] * i0i;
-                    ci[r] = rr[r] * i0i + ri[r] * i0r;
                     tq2[r] = R(2) * qr[r];
+                    if constexpr (MU == MU_INT) {
+                        cr[r] = rr[r];
+                        ci[r] = ri[r];
+                        // a = (i chi - alpha) Delta / 2 and e^{a}; moments m_j = int u^j e^{a u}
+                        R sh, chh;
+                        sincos_rev(frac_rev<R>(0.5 * tq), &sh, &chh);
+                        const R hd = R(M_PI) / R(sc.wd);                       // Delta / 2
+                        const R ar = -al * hd, ai = ch * hd;
+                        const R eh = exp_r(ar);
+                        node_moments(ar, ai, eh * chh, eh * sh, mre[r], mim[r]);
+                        // fold e^{a} Delta / 2 into the moments
+                        const R fr = hd * eh * chh, fi = hd * eh * sh;
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const R tr = mre[r][j] * fr - mim[r][j] * fi;
+                            mim[r][j] = mre[r][j] * fi + mim[r][j] * fr;
+                            mre[r][j] = tr;
+                        }
+                    } else {
+                        const R vr = qr[r] - R(1), vi = qi[r];
+                        const R inv = recip(al * al + ch * ch);
+                        const R i0r = (-al * vr + ch * vi) * inv;
+                        const R i0i = (-ch * vr - al * vi) * inv;
+                        cr[r] = rr[r] * i0r - ri[r] * i0i;
+                        ci[r] = rr[r] * i0i + ri[r] * i0r;
+                    }
                 }
                 // Goertzel state per point; s = |q|^2 is uniform over the span
                 const R ms = R(-(sc.em * sc.em));
-                R b1[PPT], b2[PPT];
-#pragma unroll
-                for (int r = 0; r < PPT; ++r) {
-                    b1[r] = R(0);
-                    b2[r] = R(0);
-                }
                 const int Kp4 = (sc.K + 3) & ~3;
-                for (int kc1 = Kp4; kc1 > 0; kc1 -= KC) {
-                    const int kc0 = kc1 > KC ? kc1 - KC : 0;
-                    const int len = kc1 - kc0;
-                    __syncthreads();  // previous readers of the staged rows are done
-                    // stage g_k(f3) = A_k exp(-zeta_k f3abs) for the tile's anti-diagonals:
-                    // an item is VW consecutive segments of a run of SRUN anti-diagonals,
-                    // one exp per segment at the run's first anti-diagonal, then the
-                    // step ratio exp(-zeta h) down the run, one vector write per row
-                    constexpr int SRUN = STAGE_RUN;
-                    constexpr int RUNS = (NAD + SRUN - 1) / SRUN;
-                    const int lenv = len / VW;
-                    for (int t = tid; t < lenv * RUNS; t += THREADS) {
-                        const int kv = t % lenv, run = t / lenv;
-                        const double x = x3b + (mb + run * SRUN + 1 - N) * h;
-                        R g[VW], rt[VW];
+                for (int n = 0; n < NN; ++n) {
+                    const int row0 = sc.off + n * sc.K;
+                    R b1[PPT], b2[PPT];
 #pragma unroll
-                        for (int e = 0; e < VW; ++e) {
-                            const int k = kc0 + kv * VW + e;
-                            g[e] = R(0);
-                            rt[e] = R(0);
-                            if (k < sc.K) {
-                                const Seg row = seg[sc.off + k];
-                                g[e] = row.A * exp_neg(row.zeta, x);
-                                rt[e] = row.ratio;
+                    for (int r = 0; r < PPT; ++r) {
+                        b1[r] = R(0);
+                        b2[r] = R(0);
+                    }
+                    for (int kc1 = Kp4; kc1 > 0; kc1 -= KC) {
+                        const int kc0 = kc1 > KC ? kc1 - KC : 0;
+                        const int len = kc1 - kc0;
+                        __syncthreads();  // previous readers of the staged rows are done
+                        // stage g_k(f3) = A_k exp(-zeta_k f3abs) for the tile's anti-diagonals:
+                        // an item is VW consecutive segments of a run of SRUN anti-diagonals,
+                        // one exp per segment at the run's first anti-diagonal, then the
+                        // step ratio exp(-zeta h) down the run, one vector write per row
+                        constexpr int SRUN = STAGE_RUN;
+                        constexpr int RUNS = (NAD + SRUN - 1) / SRUN;
+                        const int lenv = len / VW;
+                        for (int t = tid; t < lenv * RUNS; t += THREADS) {
+                            const int kv = t % lenv, run = t / lenv;
+                            const double x = x3b + (mb + run * SRUN + 1 - N) * h;
+                            R g[VW], rt[VW];
+#pragma unroll
+                            for (int e = 0; e < VW; ++e) {
+                                const int k = kc0 + kv * VW + e;
+                                g[e] = R(0);
+                                rt[e] = R(0);
+                                if (k < sc.K) {
+                                    const Seg row = seg[row0 + k];
+                                    g[e] = row.A * exp_neg(row.zeta, x);
+                                    rt[e] = row.ratio;
+                                }
+                            }
+                            Vec* dst = g_vec + (run * SRUN) * KPV + kv;
+#pragma unroll
+                            for (int q = 0; q < SRUN; ++q) {
+                                if (run * SRUN + q < NAD) dst[q * KPV] = pack_vec(g);
+#pragma unroll
+                                for (int e = 0; e < VW; ++e) g[e] *= rt[e];
                             }
                         }
-                        Vec* dst = g_vec + (run * SRUN) * KPV + kv;
-#pragma unroll
-                        for (int q = 0; q < SRUN; ++q) {
-                            if (run * SRUN + q < NAD) dst[q * KPV] = pack_vec(g);
-#pragma unroll
-                            for (int e = 0; e < VW; ++e) g[e] *= rt[e];
-                        }
-                    }
-                    __syncthreads();
-                    // every point reads its own anti-diagonal row: one base index
-                    // plus compile-time row offsets (8 rows apart per point).  Four
-                    // segments per step: b2 takes b_k, then b1 takes b_{k-1}, so the
-                    // state never moves between registers; the older state enters the
-                    // inner product, so one FMA per segment is on the dependency chain.
-                    const Vec* gb = g_vec + (li + lj) * KPV;
+                        __syncthreads();
+                        // every point reads its own anti-diagonal row: one base index
+                        // plus compile-time row offsets (8 rows apart per point).  Four
+                        // segments per step: b2 takes b_k, then b1 takes b_{k-1}, so the
+                        // state never moves between registers; the older state enters the
+                        // inner product, so one FMA per segment is on the dependency chain.
+                        const Vec* gb = g_vec + (li + lj) * KPV;
 #pragma unroll 2
-                    for (int kq = len / 4 - 1; kq >= 0; --kq) {
-                        R g0[PPT], g1[PPT], g2[PPT], g3[PPT];
+                        for (int kq = len / 4 - 1; kq >= 0; --kq) {
+                            R g0[PPT], g1[PPT], g2[PPT], g3[PPT];
 #pragma unroll
-                        for (int r = 0; r < PPT; ++r) load4(gb + r * 8 * KPV, kq, g0[r], g1[r], g2[r], g3[r]);
+                            for (int r = 0; r < PPT; ++r) load4(gb + r * 8 * KPV, kq, g0[r], g1[r], g2[r], g3[r]);
 #pragma unroll
-                        for (int r = 0; r < PPT; ++r) {
-                            b2[r] = fma(tq2[r], b1[r], fma(ms, b2[r], g3[r]));
-                            b1[r] = fma(tq2[r], b2[r], fma(ms, b1[r], g2[r]));
-                            b2[r] = fma(tq2[r], b1[r], fma(ms, b2[r], g1[r]));
-                            b1[r] = fma(tq2[r], b2[r], fma(ms, b1[r], g0[r]));
+                            for (int r = 0; r < PPT; ++r) {
+                                b2[r] = fma(tq2[r], b1[r], fma(ms, b2[r], g3[r]));
+                                b1[r] = fma(tq2[r], b2[r], fma(ms, b1[r], g2[r]));
+                                b2[r] = fma(tq2[r], b1[r], fma(ms, b2[r], g1[r]));
+                                b1[r] = fma(tq2[r], b2[r], fma(ms, b1[r], g0[r]));
+                            }
                         }
                     }
-                }
 #pragma unroll
-                for (int r = 0; r < PPT; ++r) {
-                    // P(q) = b_0 - conj(q) b_1;  Upsilon += c P
-                    if (!fb[r]) continue;
-                    const R pr = b1[r] - qr[r] * b2[r], pi = qi[r] * b2[r];
-                    ur[r] += cr[r] * pr - ci[r] * pi;
-                    ui[r] += cr[r] * pi + ci[r] * pr;
+                    for (int r = 0; r < PPT; ++r) {
+                        // P(q) = b_0 - conj(q) b_1;  Upsilon += c W_n P
+                        if (!fb[r]) continue;
+                        R pr = b1[r] - qr[r] * b2[r], pi = qi[r] * b2[r];
+                        if constexpr (MU == MU_INT) {
+                            R wr, wi;
+                            node_weight(n, mre[r], mim[r], wr, wi);
+                            const R tr = wr * pr - wi * pi;
+                            pi = wr * pi + wi * pr;
+                            pr = tr;
+                        }
+                        ur[r] += cr[r] * pr - ci[r] * pi;
+                        ui[r] += cr[r] * pi + ci[r] * pr;
+                    }
                 }
             }
 
@@ -399,7 +507,7 @@ __device__ void region_unit(const RegionArgs& a, const int u, VecOf<R>* g_vec, d
 // FP32: at most 168 VGPRs, three waves per SIMD; the surrogate-table variant
 // keeps both code paths live and takes two.
 template <typename R, int MU>
-constexpr int region_min_waves() { return sizeof(R) == 4 && MU != 2 ? 3 : 2; }
+constexpr int region_min_waves() { return sizeof(R) == 4 && (MU == MU_SEG || MU == MU_MAC) ? 3 : 2; }
 
 template <typename R, int MU>
 __global__ void __launch_bounds__(THREADS, (region_min_waves<R, MU>())) region_kernel(RegionArgs a)
@@ -654,10 +762,12 @@ hipError_t launch_region_t(const RegionArgs& a, int blocks, hipStream_t st)
 hipError_t launch_region(const RegionArgs& a, int blocks, bool fp32, hipStream_t st)
 {
     if (a.n_units == 0) return hipSuccess;
-    if (a.mu_method == 2) {
+    if (a.mu_method == MU_SUR) {
         if (!fp32 || !a.sur_tab) return hipErrorInvalidValue;   // the table path runs the FP32 integrand
-        return launch_region_t<float, 2>(a, blocks, st);
+        return launch_region_t<float, MU_SUR>(a, blocks, st);
     }
+    if (a.mu_method == MU_INT)
+        return fp32 ? launch_region_t<float, MU_INT>(a, blocks, st) : launch_region_t<double, MU_INT>(a, blocks, st);
     if (fp32)
         return a.mu_method == 0 ? launch_region_t<float, 0>(a, blocks, st) : launch_region_t<float, 1>(a, blocks, st);
     return a.mu_method == 0 ? launch_region_t<double, 0>(a, blocks, st) : launch_region_t<double, 1>(a, blocks, st);
@@ -674,8 +784,11 @@ int region_blocks_per_cu(bool fp32, int mu_method)
 {
     int n = 0;
     hipError_t e;
-    if (mu_method == 2)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, region_queue_kernel<float, 2>, THREADS, 0);
+    if (mu_method == MU_SUR)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, region_queue_kernel<float, MU_SUR>, THREADS, 0);
+    else if (mu_method == MU_INT)
+        e = fp32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, region_queue_kernel<float, MU_INT>, THREADS, 0)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, region_queue_kernel<double, MU_INT>, THREADS, 0);
     else if (fp32)
         e = mu_method == 0 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, region_queue_kernel<float, 0>, THREADS, 0)
                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, region_queue_kernel<float, 1>, THREADS, 0);

@@ -8,7 +8,8 @@ oracle):
   * the 512-link batch at 64 x 64 (the launch the benchmark times): eta of
     every CUT of two links.
 
-Bars: FP64 path vs the segment form 1e-9 relative; FP32-integrand path vs the
+Bars: FP64 path vs the segment form 1e-9 relative; the integral form
+(dz 0.25 km) vs the oracle's integral 1e-6 relative; FP32-integrand path vs the
 segment form 1e-3 relative per nonzero integral (0.004 dB); every path vs
 the integral form within 0.01 dB on D and on eta.
 """
@@ -59,11 +60,14 @@ def _check_squares(engine, wl, entries, label):
         print(f"{label}: CUT {cut}, squares {keys}", flush=True)
         g64 = engine.eval_islands(wl.numerics, cut, keys, precision=FP64)
         g32 = engine.eval_islands(wl.numerics, cut, keys, precision=FP32)
-        for (k1, k2), a64, a32 in zip(keys, g64, g32):
+        gint = engine.eval_islands(wl.numerics, cut, keys, precision=FP64, mu_method=2, dz=0.25)
+        for (k1, k2), a64, a32, ai in zip(keys, g64, g32, gint):
             seg = sq[(cut, k1, k2)]["segment"]
             integ = sq[(cut, k1, k2)]["integral"]
             scale = np.abs(seg).max() + 1e-300
             assert np.allclose(a64, seg, rtol=1e-9, atol=1e-12 * scale), (cut, k1, k2, a64, seg)
+            # the GPU integral form against the oracle's adaptive integral
+            assert np.allclose(ai, integ, rtol=1e-6, atol=1e-9 * scale), (cut, k1, k2, ai, integ)
             nz = np.abs(seg) > 1e-9 * scale
             if not nz.any():                      # no island of this square reaches the CUT
                 assert np.all(a32 == 0.0), (cut, k1, k2)
