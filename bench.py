@@ -147,6 +147,29 @@ def batched_leg(eng, n_links, n_plain, W, torch):
             "max_abs_db_batch_vs_plain": agree}
 
 
+def integral_form_leg(eng, wl, W, torch, n_cuts=10):
+    """The model's integral form (Eq. 23, 4-node product integration per 1 km
+    segment, FP64) against the closed forms on the same CUTs: the GPU
+    counterpart of the paper's integral vs closed-form time comparison."""
+    cuts = np.linspace(0, len(wl.cuts) - 1, n_cuts).astype(np.int32)
+    eng.load(wl)
+    res = {"workload": f"{n_cuts} CUTs of the benchmark link at {wl.numerics.n_grid}x{wl.numerics.n_grid}"}
+    runs = (("integral_fp64", dict(precision=W.PREC_FP64, mu_method=2)),
+            ("segment_fp64", dict(precision=W.PREC_FP64)),
+            ("segment_fp32", dict(precision=W.PREC_FP32_PHASE64)),
+            ("maclaurin_fp32", dict(precision=W.PREC_FP32_PHASE64, mu_method=1)))
+    eta = {}
+    for name, kw in runs:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        eta[name] = eng.eval_eta(wl.numerics, cuts, **kw)["eta"]
+        res[name + "_s"] = time.perf_counter() - t0
+    for name in ("segment_fp64", "segment_fp32", "maclaurin_fp32"):
+        res[name + "_max_abs_db_vs_integral"] = float(np.max(np.abs(10 * np.log10(eta[name] / eta["integral_fp64"]))))
+    res["segment_fp32_time_saving_vs_integral"] = 1.0 - res["segment_fp32_s"] / res["integral_fp64_s"]
+    return res
+
+
 def per_cut_dz_leg(eng, wl, eta_dz1, W, torch):
     """The segment form's step chosen per CUT (error model on a 32 x 32 grid,
     0.005 dB against a 0.5 km step), then the full workload with those steps."""
@@ -264,6 +287,8 @@ def main():
     ap.add_argument("--plain-links", type=int, default=48,
                     help="links of the batch evaluated one by one on the plain path for comparison")
     ap.add_argument("--per-cut-dz", type=int, default=1, help="run the per-CUT step leg (0 = skip)")
+    ap.add_argument("--integral-cuts", type=int, default=10,
+                    help="CUTs of the integral-form comparison leg (0 = skip)")
     ap.add_argument("--surrogate-points", type=int, default=1 << 22,
                     help="query points of the surrogate leg (0 = skip)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -367,6 +392,9 @@ def main():
         out["accuracy"] = {"fp32_vs_fp64_max_abs_db": float(err.max()), "fp32_vs_fp64_mean_abs_db": float(err.mean()),
                            "within_0p01_db": bool(err.max() <= 0.01)}
         out["fp64_value"] = n_cut / t64
+    if args.integral_cuts > 0:
+        log("integral form leg")
+        out["integral_form"] = integral_form_leg(eng, wl, W, torch, args.integral_cuts)
     if args.per_cut_dz:
         out["per_cut_dz"] = per_cut_dz_leg(eng, wl, eta32, W, torch)
     if args.batch_links > 0:
