@@ -444,7 +444,7 @@ __device__ void region_unit(const RegionArgs& a, const int u, VecOf<R>* g_vec, d
                         // state never moves between registers; the older state enters the
                         // inner product, so one FMA per segment is on the dependency chain.
                         const Vec* gb = g_vec + (li + lj) * KPV;
-#pragma unroll 2
+#pragma unroll 4
                         for (int kq = len / 4 - 1; kq >= 0; --kq) {
                             R g0[PPT], g1[PPT], g2[PPT], g3[PPT];
 #pragma unroll

@@ -141,3 +141,18 @@ def test_batch_rejects_bad_links(engine):
     with pytest.raises(_lib.IsrsError) as ei:
         engine.batch(links)
     assert ei.value.code == _lib.ISRS_E_LINK
+
+
+def test_batch_integral_and_maclaurin_forms(engine):
+    """The queue path runs every form of mu: batch results equal single links."""
+    links = _links()[:3]
+    b = engine.batch(links)
+    nu = links[0].numerics
+    off = b.cut_offset
+    for mu in (1, 2):
+        got = b.eval(nu, precision=FP64, mu_method=mu, dz=0.5)
+        for i, w in enumerate(links):
+            engine.load(w)
+            single = engine.eval_eta(nu, w.cuts, precision=FP64, mu_method=mu, dz=0.5)["eta"]
+            assert np.allclose(got[off[i]:off[i + 1]], single, rtol=1e-13, atol=0), (mu, i)
+    b.close()
