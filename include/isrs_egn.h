@@ -10,7 +10,9 @@
  *     terms E, F, G, H (Eqs. 18-21);
  *   - the link function Upsilon (Eq. 22), whose per-span FWM efficiency
  *     factor mu_s (Eq. 23) is taken from the segment closed form (Eqs. 7-10),
- *     or, on request, the Maclaurin closed form (Eqs. 2-6);
+ *     or, on request, the Maclaurin closed form (Eqs. 2-6), the integral
+ *     form itself (Eq. 23 by product integration), or a learned surrogate
+ *     with closed-form fallback;
  *   - the NLI coefficient eta = sigma^2 / P^3 (Eq. 11) and the NLI PSD.
  *
  * Conventions shared by every call
@@ -31,9 +33,12 @@
  *   The library copies what it needs: callers keep ownership of every
  *   buffer they pass.  No call throws across the boundary.
  *
- *   A context owns a HIP stream (borrowed or default) and device scratch
- *   that it grows on demand and frees in isrs_destroy.  Use one context per
- *   host thread; calls on one context must not overlap.
+ *   A context works on one HIP stream: the caller's, or (hip_stream NULL)
+ *   a non-blocking stream of its own, which is not ordered with the
+ *   caller's work, so device outputs of the *_dev calls are then valid
+ *   after a device or stream synchronisation.  It owns device scratch that
+ *   it grows on demand and frees in isrs_destroy.  Use one context per host
+ *   thread; calls on one context must not overlap.
  */
 #ifndef ISRS_EGN_H
 #define ISRS_EGN_H

@@ -1147,96 +1147,130 @@ int32_t eval_eta_table(isrs_ctx* c, const isrs_numerics* nu, const int32_t* cuts
 }
 }  // namespace isrs
 
+namespace isrs {
+// Status of an exception caught at the C-ABI boundary (none may cross it).
+int32_t abi_exception(isrs_ctx* c)
+{
+    try {
+        throw;
+    } catch (const std::bad_alloc&) {
+        return c ? fail(c, ISRS_E_NOMEM, "host allocation failed") : ISRS_E_NOMEM;
+    } catch (...) {
+        return c ? fail(c, ISRS_E_DEVICE, "unexpected host exception") : ISRS_E_DEVICE;
+    }
+}
+}  // namespace isrs
+
 extern "C" {
 
 const char* isrs_version(void) { return "isrs-egn 0.2 (gfx950)"; }
 
 int32_t isrs_validate_spectrum(const isrs_spectrum* s)
 {
-    if (!s) return ISRS_E_ARG;
-    return validate_spectrum_msg(s).empty() ? ISRS_OK : ISRS_E_SPECTRUM;
+    try {
+        if (!s) return ISRS_E_ARG;
+        return validate_spectrum_msg(s).empty() ? ISRS_OK : ISRS_E_SPECTRUM;
+    } catch (...) {
+        return abi_exception(nullptr);
+    }
 }
 
 int32_t isrs_validate_link(const isrs_span* sp, int32_t n, int32_t gain_mode)
 {
-    if (!sp) return ISRS_E_ARG;
-    if (n < 1 || n > MAX_SPANS) return ISRS_E_ARG;
-    return validate_link_msg(sp, n, gain_mode).empty() ? ISRS_OK : ISRS_E_LINK;
+    try {
+        if (!sp) return ISRS_E_ARG;
+        if (n < 1 || n > MAX_SPANS) return ISRS_E_ARG;
+        return validate_link_msg(sp, n, gain_mode).empty() ? ISRS_OK : ISRS_E_LINK;
+    } catch (...) {
+        return abi_exception(nullptr);
+    }
 }
 
 int32_t isrs_validate_numerics(const isrs_numerics* nu)
 {
-    return validate_numerics_msg(nu).empty() ? ISRS_OK : ISRS_E_ARG;
+    try {
+        return validate_numerics_msg(nu).empty() ? ISRS_OK : ISRS_E_ARG;
+    } catch (...) {
+        return abi_exception(nullptr);
+    }
 }
 
 int32_t isrs_create(isrs_ctx** out, int32_t device, void* hip_stream)
 {
-    g_create_error.clear();
-    if (!out) {
-        g_create_error = "out is null";
-        return ISRS_E_ARG;
-    }
-    *out = nullptr;
-    int n = 0;
-    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
-        g_create_error = "no HIP device";
-        return ISRS_E_DEVICE;
-    }
-    if (device < 0 || device >= n) {
-        g_create_error = "device ordinal out of range";
-        return ISRS_E_DEVICE;
-    }
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
-        g_create_error = "hipGetDeviceProperties failed";
-        return ISRS_E_DEVICE;
-    }
-    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
-        g_create_error = std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950";
-        return ISRS_E_DEVICE;
-    }
-    isrs_ctx* c = new (std::nothrow) isrs_ctx();
-    Workspace* w = new (std::nothrow) Workspace();
-    if (!c || !w) {
-        delete c;
-        delete w;
-        g_create_error = "host allocation failed";
-        return ISRS_E_NOMEM;
-    }
-    c->ws = w;
-    c->device = device;
-    c->n_cu = prop.multiProcessorCount;
-    if (hipSetDevice(device) != hipSuccess) {
-        delete w;
-        delete c;
-        g_create_error = "hipSetDevice failed";
-        return ISRS_E_DEVICE;
-    }
-    if (hip_stream) {
-        c->stream = reinterpret_cast<hipStream_t>(hip_stream);
-    } else {
-        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
-            delete w;
-            delete c;
-            g_create_error = "stream creation failed";
+    try {
+        g_create_error.clear();
+        if (!out) {
+            g_create_error = "out is null";
+            return ISRS_E_ARG;
+        }
+        *out = nullptr;
+        int n = 0;
+        if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
+            g_create_error = "no HIP device";
             return ISRS_E_DEVICE;
         }
-        c->own_stream = true;
+        if (device < 0 || device >= n) {
+            g_create_error = "device ordinal out of range";
+            return ISRS_E_DEVICE;
+        }
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+            g_create_error = "hipGetDeviceProperties failed";
+            return ISRS_E_DEVICE;
+        }
+        if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+            g_create_error = std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950";
+            return ISRS_E_DEVICE;
+        }
+        isrs_ctx* c = new (std::nothrow) isrs_ctx();
+        Workspace* w = new (std::nothrow) Workspace();
+        if (!c || !w) {
+            delete c;
+            delete w;
+            g_create_error = "host allocation failed";
+            return ISRS_E_NOMEM;
+        }
+        c->ws = w;
+        c->device = device;
+        c->n_cu = prop.multiProcessorCount;
+        if (hipSetDevice(device) != hipSuccess) {
+            delete w;
+            delete c;
+            g_create_error = "hipSetDevice failed";
+            return ISRS_E_DEVICE;
+        }
+        if (hip_stream) {
+            c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+        } else {
+            if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+                delete w;
+                delete c;
+                g_create_error = "stream creation failed";
+                return ISRS_E_DEVICE;
+            }
+            c->own_stream = true;
+        }
+        *out = c;
+        return ISRS_OK;
+    } catch (...) {
+        return abi_exception(nullptr);
     }
-    *out = c;
-    return ISRS_OK;
 }
 
 int32_t isrs_destroy(isrs_ctx* c)
 {
-    if (!c) return ISRS_E_ARG;
-    (void)hipSetDevice(c->device);
-    (void)hipStreamSynchronize(c->stream);
-    c->ws->release();
-    delete c->ws;
-    if (c->own_stream) (void)hipStreamDestroy(c->stream);
-    delete c;
-    return ISRS_OK;
+    try {
+        if (!c) return ISRS_E_ARG;
+        (void)hipSetDevice(c->device);
+        (void)hipStreamSynchronize(c->stream);
+        c->ws->release();
+        delete c->ws;
+        if (c->own_stream) (void)hipStreamDestroy(c->stream);
+        delete c;
+        return ISRS_OK;
+    } catch (...) {
+        return abi_exception(c);
+    }
 }
 
 const char* isrs_last_error(const isrs_ctx* c)
@@ -1247,399 +1281,471 @@ const char* isrs_last_error(const isrs_ctx* c)
 
 int32_t isrs_set_spectrum(isrs_ctx* c, const isrs_spectrum* s)
 {
-    if (!c) return ISRS_E_ARG;
-    if (!s) return fail(c, ISRS_E_ARG, "spectrum is null");
-    std::string m = validate_spectrum_msg(s);
-    if (!m.empty()) return fail(c, ISRS_E_SPECTRUM, m);
-    c->n_ch = s->n_ch;
-    c->spacing = s->spacing_thz;
-    c->rs = s->symbol_rate_thz;
-    c->rolloff = s->rolloff;
-    c->f_center = s->f_center_thz;
-    c->power.assign(s->power_w, s->power_w + s->n_ch);
-    c->phi.assign(s->phi, s->phi + s->n_ch);
-    c->psi.assign(s->psi, s->psi + s->n_ch);
-    c->has_spec = true;
-    c->err.clear();
-    return ISRS_OK;
+    try {
+        if (!c) return ISRS_E_ARG;
+        if (!s) return fail(c, ISRS_E_ARG, "spectrum is null");
+        std::string m = validate_spectrum_msg(s);
+        if (!m.empty()) return fail(c, ISRS_E_SPECTRUM, m);
+        c->n_ch = s->n_ch;
+        c->spacing = s->spacing_thz;
+        c->rs = s->symbol_rate_thz;
+        c->rolloff = s->rolloff;
+        c->f_center = s->f_center_thz;
+        c->power.assign(s->power_w, s->power_w + s->n_ch);
+        c->phi.assign(s->phi, s->phi + s->n_ch);
+        c->psi.assign(s->psi, s->psi + s->n_ch);
+        c->has_spec = true;
+        c->err.clear();
+        return ISRS_OK;
+    } catch (...) {
+        return abi_exception(c);
+    }
 }
 
 int32_t isrs_set_link(isrs_ctx* c, const isrs_span* spans, int32_t n, int32_t gain_mode)
 {
-    if (!c) return ISRS_E_ARG;
-    if (!spans || n < 1 || n > MAX_SPANS) return fail(c, ISRS_E_ARG, "bad span array or count");
-    std::string m = validate_link_msg(spans, n, gain_mode);
-    if (!m.empty()) return fail(c, ISRS_E_LINK, m);
-    c->spans.assign(spans, spans + n);
-    c->gain_mode = gain_mode;
-    c->has_link = true;
-    c->err.clear();
-    return ISRS_OK;
+    try {
+        if (!c) return ISRS_E_ARG;
+        if (!spans || n < 1 || n > MAX_SPANS) return fail(c, ISRS_E_ARG, "bad span array or count");
+        std::string m = validate_link_msg(spans, n, gain_mode);
+        if (!m.empty()) return fail(c, ISRS_E_LINK, m);
+        c->spans.assign(spans, spans + n);
+        c->gain_mode = gain_mode;
+        c->has_link = true;
+        c->err.clear();
+        return ISRS_OK;
+    } catch (...) {
+        return abi_exception(c);
+    }
 }
 
 int32_t isrs_set_ptot_override(isrs_ctx* c, double ptot_w)
 {
-    if (!c) return ISRS_E_ARG;
-    if (!(is_fin(ptot_w) && ptot_w >= 0)) return fail(c, ISRS_E_ARG, "ptot override must be finite and >= 0");
-    c->ptot_override = ptot_w;
-    return ISRS_OK;
+    try {
+        if (!c) return ISRS_E_ARG;
+        if (!(is_fin(ptot_w) && ptot_w >= 0)) return fail(c, ISRS_E_ARG, "ptot override must be finite and >= 0");
+        c->ptot_override = ptot_w;
+        return ISRS_OK;
+    } catch (...) {
+        return abi_exception(c);
+    }
 }
 
 int32_t isrs_set_profiling(isrs_ctx* c, int32_t profile)
 {
-    if (!c) return ISRS_E_ARG;
-    c->profiling = profile != 0;
-    return ISRS_OK;
+    try {
+        if (!c) return ISRS_E_ARG;
+        c->profiling = profile != 0;
+        return ISRS_OK;
+    } catch (...) {
+        return abi_exception(c);
+    }
 }
 
 int32_t isrs_get_stats(const isrs_ctx* c, isrs_stats* out)
 {
-    if (!c || !out) return ISRS_E_ARG;
-    *out = c->stats;
-    return ISRS_OK;
+    try {
+        if (!c || !out) return ISRS_E_ARG;
+        *out = c->stats;
+        return ISRS_OK;
+    } catch (...) {
+        return abi_exception(nullptr);
+    }
 }
 
 int32_t isrs_eval_eta_dev(isrs_ctx* c, const isrs_numerics* nu, const int32_t* cuts, int32_t n_cut, double* eta_dev,
                           double* sigma2_dev, double* terms_dev)
 {
-    if (!c) return ISRS_E_ARG;
-    if (!eta_dev) return fail(c, ISRS_E_ARG, "eta output is null");
-    return evaluate(c, nu, cuts, n_cut, nullptr, 0, eta_dev, sigma2_dev, terms_dev, nullptr, nullptr);
+    try {
+        if (!c) return ISRS_E_ARG;
+        if (!eta_dev) return fail(c, ISRS_E_ARG, "eta output is null");
+        return evaluate(c, nu, cuts, n_cut, nullptr, 0, eta_dev, sigma2_dev, terms_dev, nullptr, nullptr);
+    } catch (...) {
+        return abi_exception(c);
+    }
 }
 
 int32_t isrs_eval_eta(isrs_ctx* c, const isrs_numerics* nu, const int32_t* cuts, int32_t n_cut, double* eta,
                       double* sigma2, double* terms)
 {
-    if (!c) return ISRS_E_ARG;
-    if (!eta) return fail(c, ISRS_E_ARG, "eta output is null");
-    if (n_cut < 1) return fail(c, ISRS_E_ARG, "need at least one CUT");
-    HIP_TRY(c, hipSetDevice(c->device));
-    const size_t n = (size_t)n_cut;
-    HIP_TRY(c, c->ws->out.ensure(n * 7 * sizeof(double)));
-    double* d = c->ws->out.as<double>();
-    int32_t rc = evaluate(c, nu, cuts, n_cut, nullptr, 0, d, d + n, d + 2 * n, nullptr, nullptr);
-    if (rc) return rc;
-    std::vector<double> h(n * 7);
-    HIP_TRY(c, hipMemcpyAsync(h.data(), d, n * 7 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    for (size_t q = 0; q < n; ++q) {
-        if (!is_fin(h[q]) || !is_fin(h[n + q])) return fail(c, ISRS_E_NUMERIC, "non-finite NLI result");
-        eta[q] = h[q];
-        if (sigma2) sigma2[q] = h[n + q];
-        if (terms)
-            for (int u = 0; u < 5; ++u) terms[q * 5 + u] = h[2 * n + q * 5 + u];
+    try {
+        if (!c) return ISRS_E_ARG;
+        if (!eta) return fail(c, ISRS_E_ARG, "eta output is null");
+        if (n_cut < 1) return fail(c, ISRS_E_ARG, "need at least one CUT");
+        HIP_TRY(c, hipSetDevice(c->device));
+        const size_t n = (size_t)n_cut;
+        HIP_TRY(c, c->ws->out.ensure(n * 7 * sizeof(double)));
+        double* d = c->ws->out.as<double>();
+        int32_t rc = evaluate(c, nu, cuts, n_cut, nullptr, 0, d, d + n, d + 2 * n, nullptr, nullptr);
+        if (rc) return rc;
+        std::vector<double> h(n * 7);
+        HIP_TRY(c, hipMemcpyAsync(h.data(), d, n * 7 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        for (size_t q = 0; q < n; ++q) {
+            if (!is_fin(h[q]) || !is_fin(h[n + q])) return fail(c, ISRS_E_NUMERIC, "non-finite NLI result");
+            eta[q] = h[q];
+            if (sigma2) sigma2[q] = h[n + q];
+            if (terms)
+                for (int u = 0; u < 5; ++u) terms[q * 5 + u] = h[2 * n + q * 5 + u];
+        }
+        return ISRS_OK;
+    } catch (...) {
+        return abi_exception(c);
     }
-    return ISRS_OK;
 }
 
 int32_t isrs_eval_eta_dz(isrs_ctx* c, const isrs_numerics* nu, const int32_t* cuts, int32_t n_cut,
                          const double* dz_km, double* eta, double* sigma2, double* terms)
 {
-    if (!c) return ISRS_E_ARG;
-    if (!eta || !dz_km) return fail(c, ISRS_E_ARG, "eta output or step array is null");
-    if (n_cut < 1) return fail(c, ISRS_E_ARG, "need at least one CUT");
-    HIP_TRY(c, hipSetDevice(c->device));
-    const size_t n = (size_t)n_cut;
-    HIP_TRY(c, c->ws->out.ensure(n * 7 * sizeof(double)));
-    double* d = c->ws->out.as<double>();
-    std::vector<int> order;
-    int32_t rc = evaluate(c, nu, cuts, n_cut, nullptr, 0, d, d + n, d + 2 * n, nullptr, nullptr, nullptr, dz_km, &order);
-    if (rc) return rc;
-    std::vector<double> h(n * 7);
-    HIP_TRY(c, hipMemcpyAsync(h.data(), d, n * 7 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    for (size_t pos = 0; pos < n; ++pos) {
-        const size_t q = (size_t)order[pos];
-        if (!is_fin(h[pos]) || !is_fin(h[n + pos])) return fail(c, ISRS_E_NUMERIC, "non-finite NLI result");
-        eta[q] = h[pos];
-        if (sigma2) sigma2[q] = h[n + pos];
-        if (terms)
-            for (int u = 0; u < 5; ++u) terms[q * 5 + u] = h[2 * n + pos * 5 + u];
+    try {
+        if (!c) return ISRS_E_ARG;
+        if (!eta || !dz_km) return fail(c, ISRS_E_ARG, "eta output or step array is null");
+        if (n_cut < 1) return fail(c, ISRS_E_ARG, "need at least one CUT");
+        HIP_TRY(c, hipSetDevice(c->device));
+        const size_t n = (size_t)n_cut;
+        HIP_TRY(c, c->ws->out.ensure(n * 7 * sizeof(double)));
+        double* d = c->ws->out.as<double>();
+        std::vector<int> order;
+        int32_t rc = evaluate(c, nu, cuts, n_cut, nullptr, 0, d, d + n, d + 2 * n, nullptr, nullptr, nullptr, dz_km, &order);
+        if (rc) return rc;
+        std::vector<double> h(n * 7);
+        HIP_TRY(c, hipMemcpyAsync(h.data(), d, n * 7 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        for (size_t pos = 0; pos < n; ++pos) {
+            const size_t q = (size_t)order[pos];
+            if (!is_fin(h[pos]) || !is_fin(h[n + pos])) return fail(c, ISRS_E_NUMERIC, "non-finite NLI result");
+            eta[q] = h[pos];
+            if (sigma2) sigma2[q] = h[n + pos];
+            if (terms)
+                for (int u = 0; u < 5; ++u) terms[q * 5 + u] = h[2 * n + pos * 5 + u];
+        }
+        return ISRS_OK;
+    } catch (...) {
+        return abi_exception(c);
     }
-    return ISRS_OK;
 }
 
 int32_t isrs_choose_dz(isrs_ctx* c, const isrs_numerics* nu, const int32_t* cuts, int32_t n_cut,
                        const double* candidates, int32_t n_cand, double target_db, double* dz_out,
                        double* err_db_out)
 {
-    if (!c) return ISRS_E_ARG;
-    if (!nu || !cuts || !candidates || !dz_out || n_cut < 1 || n_cand < 1)
-        return fail(c, ISRS_E_ARG, "null argument or empty candidate / CUT list");
-    if (!(is_fin(target_db) && target_db >= 0)) return fail(c, ISRS_E_ARG, "target must be finite and >= 0");
-    std::vector<double> cand(candidates, candidates + n_cand);
-    for (double v : cand)
-        if (!(is_fin(v) && v > 0)) return fail(c, ISRS_E_ARG, "candidate steps must be finite and > 0");
-    std::sort(cand.begin(), cand.end());
-    const size_t n = (size_t)n_cut;
-    std::vector<double> ref(n), cur(n);
-    isrs_numerics t = *nu;
-    t.dz_km = cand[0];
-    int32_t rc = isrs_eval_eta(c, &t, cuts, n_cut, ref.data(), nullptr, nullptr);
-    if (rc) return rc;
-    for (size_t q = 0; q < n; ++q) dz_out[q] = cand[0];
-    for (int i = 0; i < n_cand; ++i) {
-        if (i > 0) {
-            t.dz_km = cand[i];
-            if ((rc = isrs_eval_eta(c, &t, cuts, n_cut, cur.data(), nullptr, nullptr))) return rc;
-        } else {
-            cur = ref;
+    try {
+        if (!c) return ISRS_E_ARG;
+        if (!nu || !cuts || !candidates || !dz_out || n_cut < 1 || n_cand < 1)
+            return fail(c, ISRS_E_ARG, "null argument or empty candidate / CUT list");
+        if (!(is_fin(target_db) && target_db >= 0)) return fail(c, ISRS_E_ARG, "target must be finite and >= 0");
+        std::vector<double> cand(candidates, candidates + n_cand);
+        for (double v : cand)
+            if (!(is_fin(v) && v > 0)) return fail(c, ISRS_E_ARG, "candidate steps must be finite and > 0");
+        std::sort(cand.begin(), cand.end());
+        const size_t n = (size_t)n_cut;
+        std::vector<double> ref(n), cur(n);
+        isrs_numerics t = *nu;
+        t.dz_km = cand[0];
+        int32_t rc = isrs_eval_eta(c, &t, cuts, n_cut, ref.data(), nullptr, nullptr);
+        if (rc) return rc;
+        for (size_t q = 0; q < n; ++q) dz_out[q] = cand[0];
+        for (int i = 0; i < n_cand; ++i) {
+            if (i > 0) {
+                t.dz_km = cand[i];
+                if ((rc = isrs_eval_eta(c, &t, cuts, n_cut, cur.data(), nullptr, nullptr))) return rc;
+            } else {
+                cur = ref;
+            }
+            for (size_t q = 0; q < n; ++q) {
+                const double e = 10.0 * std::log10(cur[q] / ref[q]);
+                if (err_db_out) err_db_out[(size_t)i * n + q] = e;
+                if (std::fabs(e) <= target_db) dz_out[q] = std::max(dz_out[q], cand[i]);
+            }
         }
-        for (size_t q = 0; q < n; ++q) {
-            const double e = 10.0 * std::log10(cur[q] / ref[q]);
-            if (err_db_out) err_db_out[(size_t)i * n + q] = e;
-            if (std::fabs(e) <= target_db) dz_out[q] = std::max(dz_out[q], cand[i]);
-        }
+        return ISRS_OK;
+    } catch (...) {
+        return abi_exception(c);
     }
-    return ISRS_OK;
 }
 
 int32_t isrs_eval_psd(isrs_ctx* c, const isrs_numerics* nu, const int32_t* cuts, int32_t n_cut, double* f_thz,
                       double* psd)
 {
-    if (!c) return ISRS_E_ARG;
-    if (!f_thz || !psd) return fail(c, ISRS_E_ARG, "output is null");
-    std::string m = validate_numerics_msg(nu);
-    if (!m.empty()) return fail(c, ISRS_E_ARG, m);
-    if (n_cut < 1) return fail(c, ISRS_E_ARG, "need at least one CUT");
-    HIP_TRY(c, hipSetDevice(c->device));
-    const size_t n = (size_t)n_cut, nf = (size_t)nu->n_f;
-    HIP_TRY(c, c->ws->out.ensure(n * (1 + nf) * sizeof(double)));
-    double* d = c->ws->out.as<double>();
-    int32_t rc = evaluate(c, nu, cuts, n_cut, nullptr, 0, d, nullptr, nullptr, d + n, nullptr);
-    if (rc) return rc;
-    std::vector<double> h(n * nf);
-    HIP_TRY(c, hipMemcpyAsync(h.data(), d + n, n * nf * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    for (size_t q = 0; q < n; ++q)
-        for (size_t k = 0; k < nf; ++k) {
-            if (!is_fin(h[q * nf + k])) return fail(c, ISRS_E_NUMERIC, "non-finite PSD");
-            psd[q * nf + k] = h[q * nf + k];
-            f_thz[q * nf + k] = nf == 1 ? 0.0 : -0.5 * c->rs + (k + 0.5) * c->rs / nf;
-        }
-    return ISRS_OK;
+    try {
+        if (!c) return ISRS_E_ARG;
+        if (!f_thz || !psd) return fail(c, ISRS_E_ARG, "output is null");
+        std::string m = validate_numerics_msg(nu);
+        if (!m.empty()) return fail(c, ISRS_E_ARG, m);
+        if (n_cut < 1) return fail(c, ISRS_E_ARG, "need at least one CUT");
+        HIP_TRY(c, hipSetDevice(c->device));
+        const size_t n = (size_t)n_cut, nf = (size_t)nu->n_f;
+        HIP_TRY(c, c->ws->out.ensure(n * (1 + nf) * sizeof(double)));
+        double* d = c->ws->out.as<double>();
+        int32_t rc = evaluate(c, nu, cuts, n_cut, nullptr, 0, d, nullptr, nullptr, d + n, nullptr);
+        if (rc) return rc;
+        std::vector<double> h(n * nf);
+        HIP_TRY(c, hipMemcpyAsync(h.data(), d + n, n * nf * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        for (size_t q = 0; q < n; ++q)
+            for (size_t k = 0; k < nf; ++k) {
+                if (!is_fin(h[q * nf + k])) return fail(c, ISRS_E_NUMERIC, "non-finite PSD");
+                psd[q * nf + k] = h[q * nf + k];
+                f_thz[q * nf + k] = nf == 1 ? 0.0 : -0.5 * c->rs + (k + 0.5) * c->rs / nf;
+            }
+        return ISRS_OK;
+    } catch (...) {
+        return abi_exception(c);
+    }
 }
 
 int32_t isrs_eval_islands(isrs_ctx* c, const isrs_numerics* nu, int32_t cut, const int32_t* kappa12, int32_t m,
                           double* partials)
 {
-    if (!c) return ISRS_E_ARG;
-    if (!kappa12 || m < 1 || !partials) return fail(c, ISRS_E_ARG, "bad square list or output");
-    if (nu && nu->n_f != 1) return fail(c, ISRS_E_ARG, "island partials are defined at f = 0 (n_f = 1)");
-    int32_t cuts[1] = {cut};
-    int32_t rc = evaluate(c, nu, cuts, 1, kappa12, m, nullptr, nullptr, nullptr, nullptr, partials);
-    if (rc) return rc;
-    for (size_t t = 0; t < (size_t)m * 15; ++t)
-        if (!is_fin(partials[t])) return fail(c, ISRS_E_NUMERIC, "non-finite island partial");
-    return ISRS_OK;
+    try {
+        if (!c) return ISRS_E_ARG;
+        if (!kappa12 || m < 1 || !partials) return fail(c, ISRS_E_ARG, "bad square list or output");
+        if (nu && nu->n_f != 1) return fail(c, ISRS_E_ARG, "island partials are defined at f = 0 (n_f = 1)");
+        int32_t cuts[1] = {cut};
+        int32_t rc = evaluate(c, nu, cuts, 1, kappa12, m, nullptr, nullptr, nullptr, nullptr, partials);
+        if (rc) return rc;
+        for (size_t t = 0; t < (size_t)m * 15; ++t)
+            if (!is_fin(partials[t])) return fail(c, ISRS_E_NUMERIC, "non-finite island partial");
+        return ISRS_OK;
+    } catch (...) {
+        return abi_exception(c);
+    }
 }
 
 int32_t isrs_batch_create(isrs_ctx* c, const isrs_link_batch* in, isrs_batch** out)
 {
-    if (!c) return ISRS_E_ARG;
-    if (!in || !out) return fail(c, ISRS_E_ARG, "batch or output is null");
-    *out = nullptr;
-    if (in->n_links < 1 || !in->ch_offset || !in->span_offset || !in->spacing_thz || !in->symbol_rate_thz ||
-        !in->rolloff || !in->power_w || !in->phi || !in->psi || !in->spans)
-        return fail(c, ISRS_E_ARG, "batch arrays must not be null and n_links >= 1");
-    if ((in->cut_offset == nullptr) != (in->cuts == nullptr))
-        return fail(c, ISRS_E_ARG, "cut_offset and cuts must both be set or both be null");
-    isrs_batch* b = new (std::nothrow) isrs_batch();
-    if (!b) return fail(c, ISRS_E_NOMEM, "host allocation failed");
-    b->ctx = c;
-    b->n_links = in->n_links;
-    const int nl = in->n_links;
-    b->cut_off.push_back(0);
-    for (int l = 0; l < nl; ++l) {
-        const int c0 = in->ch_offset[l], c1 = in->ch_offset[l + 1];
-        const int s0 = in->span_offset[l], s1 = in->span_offset[l + 1];
-        const std::string where = "link " + std::to_string(l) + ": ";
-        if (c0 < 0 || c1 <= c0 || s0 < 0 || s1 <= s0 || (l > 0 && (c0 != in->ch_offset[l] || s0 != in->span_offset[l]))) {
-            delete b;
-            return fail(c, ISRS_E_ARG, where + "bad channel or span offsets");
-        }
-        std::string m = validate_spectrum_fields(c1 - c0, in->spacing_thz[l], in->symbol_rate_thz[l],
-                                                 in->rolloff[l], in->power_w + c0, in->phi + c0, in->psi + c0);
-        if (!m.empty()) {
-            delete b;
-            return fail(c, ISRS_E_SPECTRUM, where + m);
-        }
-        const int gm = in->gain_mode ? in->gain_mode[l] : ISRS_GAIN_EQUALIZED;
-        m = validate_link_msg(in->spans + s0, s1 - s0, gm);
-        if (!m.empty()) {
-            delete b;
-            return fail(c, ISRS_E_LINK, where + m);
-        }
-        if (in->cuts) {
-            const int q0 = in->cut_offset[l], q1 = in->cut_offset[l + 1];
-            if (q0 < 0 || q1 < q0 || q0 != b->cut_off.back()) {
+    try {
+        if (!c) return ISRS_E_ARG;
+        if (!in || !out) return fail(c, ISRS_E_ARG, "batch or output is null");
+        *out = nullptr;
+        if (in->n_links < 1 || !in->ch_offset || !in->span_offset || !in->spacing_thz || !in->symbol_rate_thz ||
+            !in->rolloff || !in->power_w || !in->phi || !in->psi || !in->spans)
+            return fail(c, ISRS_E_ARG, "batch arrays must not be null and n_links >= 1");
+        if ((in->cut_offset == nullptr) != (in->cuts == nullptr))
+            return fail(c, ISRS_E_ARG, "cut_offset and cuts must both be set or both be null");
+        isrs_batch* b = new (std::nothrow) isrs_batch();
+        if (!b) return fail(c, ISRS_E_NOMEM, "host allocation failed");
+        b->ctx = c;
+        b->n_links = in->n_links;
+        const int nl = in->n_links;
+        b->cut_off.push_back(0);
+        for (int l = 0; l < nl; ++l) {
+            const int c0 = in->ch_offset[l], c1 = in->ch_offset[l + 1];
+            const int s0 = in->span_offset[l], s1 = in->span_offset[l + 1];
+            const std::string where = "link " + std::to_string(l) + ": ";
+            if (c0 < 0 || c1 <= c0 || s0 < 0 || s1 <= s0 || (l > 0 && (c0 != in->ch_offset[l] || s0 != in->span_offset[l]))) {
                 delete b;
-                return fail(c, ISRS_E_ARG, where + "bad cut offsets");
+                return fail(c, ISRS_E_ARG, where + "bad channel or span offsets");
             }
-            for (int q = q0; q < q1; ++q) {
-                const int k = in->cuts[q];
-                if (k < 0 || k >= c1 - c0 || !(in->power_w[c0 + k] > 0)) {
+            std::string m = validate_spectrum_fields(c1 - c0, in->spacing_thz[l], in->symbol_rate_thz[l],
+                                                     in->rolloff[l], in->power_w + c0, in->phi + c0, in->psi + c0);
+            if (!m.empty()) {
+                delete b;
+                return fail(c, ISRS_E_SPECTRUM, where + m);
+            }
+            const int gm = in->gain_mode ? in->gain_mode[l] : ISRS_GAIN_EQUALIZED;
+            m = validate_link_msg(in->spans + s0, s1 - s0, gm);
+            if (!m.empty()) {
+                delete b;
+                return fail(c, ISRS_E_LINK, where + m);
+            }
+            if (in->cuts) {
+                const int q0 = in->cut_offset[l], q1 = in->cut_offset[l + 1];
+                if (q0 < 0 || q1 < q0 || q0 != b->cut_off.back()) {
                     delete b;
-                    return fail(c, ISRS_E_ARG, where + "CUT out of range or inactive");
+                    return fail(c, ISRS_E_ARG, where + "bad cut offsets");
                 }
-                b->cuts.push_back(k);
+                for (int q = q0; q < q1; ++q) {
+                    const int k = in->cuts[q];
+                    if (k < 0 || k >= c1 - c0 || !(in->power_w[c0 + k] > 0)) {
+                        delete b;
+                        return fail(c, ISRS_E_ARG, where + "CUT out of range or inactive");
+                    }
+                    b->cuts.push_back(k);
+                }
+            } else {
+                for (int k = 0; k < c1 - c0; ++k)
+                    if (in->power_w[c0 + k] > 0) b->cuts.push_back(k);
             }
-        } else {
-            for (int k = 0; k < c1 - c0; ++k)
-                if (in->power_w[c0 + k] > 0) b->cuts.push_back(k);
+            b->cut_off.push_back((int)b->cuts.size());
+            b->spacing.push_back(in->spacing_thz[l]);
+            b->rs.push_back(in->symbol_rate_thz[l]);
+            b->rolloff.push_back(in->rolloff[l]);
+            b->gain.push_back(gm);
         }
-        b->cut_off.push_back((int)b->cuts.size());
-        b->spacing.push_back(in->spacing_thz[l]);
-        b->rs.push_back(in->symbol_rate_thz[l]);
-        b->rolloff.push_back(in->rolloff[l]);
-        b->gain.push_back(gm);
+        const int nch = in->ch_offset[nl], nsp = in->span_offset[nl];
+        b->ch_off.assign(in->ch_offset, in->ch_offset + nl + 1);
+        b->span_off.assign(in->span_offset, in->span_offset + nl + 1);
+        b->power.assign(in->power_w, in->power_w + nch);
+        b->phi.assign(in->phi, in->phi + nch);
+        b->psi.assign(in->psi, in->psi + nch);
+        b->spans.assign(in->spans, in->spans + nsp);
+        b->n_cuts = (int64_t)b->cuts.size();
+        b->tuning.mode = 1;  // queue by default for batches
+        *out = b;
+        return ISRS_OK;
+    } catch (...) {
+        return abi_exception(c);
     }
-    const int nch = in->ch_offset[nl], nsp = in->span_offset[nl];
-    b->ch_off.assign(in->ch_offset, in->ch_offset + nl + 1);
-    b->span_off.assign(in->span_offset, in->span_offset + nl + 1);
-    b->power.assign(in->power_w, in->power_w + nch);
-    b->phi.assign(in->phi, in->phi + nch);
-    b->psi.assign(in->psi, in->psi + nch);
-    b->spans.assign(in->spans, in->spans + nsp);
-    b->n_cuts = (int64_t)b->cuts.size();
-    b->tuning.mode = 1;  // queue by default for batches
-    *out = b;
-    return ISRS_OK;
 }
 
 int32_t isrs_batch_destroy(isrs_batch* b)
 {
-    if (!b) return ISRS_E_ARG;
-    if (b->ctx) {
-        (void)hipSetDevice(b->ctx->device);
-        (void)hipStreamSynchronize(b->ctx->stream);
+    try {
+        if (!b) return ISRS_E_ARG;
+        if (b->ctx) {
+            (void)hipSetDevice(b->ctx->device);
+            (void)hipStreamSynchronize(b->ctx->stream);
+        }
+        b->drop_graph();
+        b->ws.release();
+        b->out.release();
+        delete b;
+        return ISRS_OK;
+    } catch (...) {
+        return abi_exception(nullptr);
     }
-    b->drop_graph();
-    b->ws.release();
-    b->out.release();
-    delete b;
-    return ISRS_OK;
 }
 
 int32_t isrs_batch_num_cuts(const isrs_batch* b, int64_t* n)
 {
-    if (!b || !n) return ISRS_E_ARG;
-    *n = b->n_cuts;
-    return ISRS_OK;
+    try {
+        if (!b || !n) return ISRS_E_ARG;
+        *n = b->n_cuts;
+        return ISRS_OK;
+    } catch (...) {
+        return abi_exception(nullptr);
+    }
 }
 
 int32_t isrs_batch_eval_dev(isrs_ctx* c, isrs_batch* b, const isrs_numerics* nu, double* eta_dev)
 {
-    if (!c) return ISRS_E_ARG;
-    if (!b || !eta_dev) return fail(c, ISRS_E_ARG, "batch or output is null");
-    if (b->ctx != c) return fail(c, ISRS_E_ARG, "batch belongs to another context");
-    std::string m = validate_numerics_msg(nu);
-    if (!m.empty()) return fail(c, ISRS_E_ARG, m);
-    HIP_TRY(c, hipSetDevice(c->device));
-    auto t0 = std::chrono::steady_clock::now();
-    if (!b->planned || !same_numerics(b->key, *nu)) {
-        int32_t rc = batch_plan(c, b, nu);
-        if (rc) return rc;
+    try {
+        if (!c) return ISRS_E_ARG;
+        if (!b || !eta_dev) return fail(c, ISRS_E_ARG, "batch or output is null");
+        if (b->ctx != c) return fail(c, ISRS_E_ARG, "batch belongs to another context");
+        std::string m = validate_numerics_msg(nu);
+        if (!m.empty()) return fail(c, ISRS_E_ARG, m);
+        HIP_TRY(c, hipSetDevice(c->device));
+        auto t0 = std::chrono::steady_clock::now();
+        if (!b->planned || !same_numerics(b->key, *nu)) {
+            int32_t rc = batch_plan(c, b, nu);
+            if (rc) return rc;
+        }
+        auto t1 = std::chrono::steady_clock::now();
+        int32_t rc = batch_run(c, b, eta_dev, true);
+        c->stats.host_prep_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+        return rc;
+    } catch (...) {
+        return abi_exception(c);
     }
-    auto t1 = std::chrono::steady_clock::now();
-    int32_t rc = batch_run(c, b, eta_dev, true);
-    c->stats.host_prep_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
-    return rc;
 }
 
 int32_t isrs_batch_eval(isrs_ctx* c, isrs_batch* b, const isrs_numerics* nu, double* eta)
 {
-    if (!c) return ISRS_E_ARG;
-    if (!b || !eta) return fail(c, ISRS_E_ARG, "batch or output is null");
-    if (b->ctx != c) return fail(c, ISRS_E_ARG, "batch belongs to another context");
-    std::string m = validate_numerics_msg(nu);
-    if (!m.empty()) return fail(c, ISRS_E_ARG, m);
-    HIP_TRY(c, hipSetDevice(c->device));
-    if (!b->planned || !same_numerics(b->key, *nu)) {
-        int32_t rc = batch_plan(c, b, nu);
+    try {
+        if (!c) return ISRS_E_ARG;
+        if (!b || !eta) return fail(c, ISRS_E_ARG, "batch or output is null");
+        if (b->ctx != c) return fail(c, ISRS_E_ARG, "batch belongs to another context");
+        std::string m = validate_numerics_msg(nu);
+        if (!m.empty()) return fail(c, ISRS_E_ARG, m);
+        HIP_TRY(c, hipSetDevice(c->device));
+        if (!b->planned || !same_numerics(b->key, *nu)) {
+            int32_t rc = batch_plan(c, b, nu);
+            if (rc) return rc;
+        }
+        int32_t rc = batch_run(c, b, b->out.as<double>(), true);
         if (rc) return rc;
+        std::vector<double> h(b->n_cuts);
+        HIP_TRY(c, hipMemcpyAsync(h.data(), b->out.p, b->n_cuts * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        for (int64_t q = 0; q < b->n_cuts; ++q) {
+            if (!is_fin(h[q])) return fail(c, ISRS_E_NUMERIC, "non-finite NLI result");
+            eta[q] = h[q];
+        }
+        return ISRS_OK;
+    } catch (...) {
+        return abi_exception(c);
     }
-    int32_t rc = batch_run(c, b, b->out.as<double>(), true);
-    if (rc) return rc;
-    std::vector<double> h(b->n_cuts);
-    HIP_TRY(c, hipMemcpyAsync(h.data(), b->out.p, b->n_cuts * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    for (int64_t q = 0; q < b->n_cuts; ++q) {
-        if (!is_fin(h[q])) return fail(c, ISRS_E_NUMERIC, "non-finite NLI result");
-        eta[q] = h[q];
-    }
-    return ISRS_OK;
 }
 
 int32_t isrs_batch_get_tuning(const isrs_batch* b, int32_t* mode, int32_t* bpc, int32_t* sort, int32_t* strips)
 {
-    if (!b) return ISRS_E_ARG;
-    if (mode) *mode = b->tuning.mode;
-    if (bpc) *bpc = b->tuning.blocks_per_cu;
-    if (sort) *sort = b->tuning.sort;
-    if (strips) *strips = b->planned ? b->plan.spb : b->tuning.spb;
-    return ISRS_OK;
+    try {
+        if (!b) return ISRS_E_ARG;
+        if (mode) *mode = b->tuning.mode;
+        if (bpc) *bpc = b->tuning.blocks_per_cu;
+        if (sort) *sort = b->tuning.sort;
+        if (strips) *strips = b->planned ? b->plan.spb : b->tuning.spb;
+        return ISRS_OK;
+    } catch (...) {
+        return abi_exception(nullptr);
+    }
 }
 
 int32_t isrs_autotune(isrs_ctx* c, isrs_batch* b, const isrs_numerics* nu, const char* cache_path)
 {
-    if (!c) return ISRS_E_ARG;
-    if (!b) return fail(c, ISRS_E_ARG, "batch is null");
-    if (b->ctx != c) return fail(c, ISRS_E_ARG, "batch belongs to another context");
-    std::string m = validate_numerics_msg(nu);
-    if (!m.empty()) return fail(c, ISRS_E_ARG, m);
-    HIP_TRY(c, hipSetDevice(c->device));
-    hipDeviceProp_t prop;
-    HIP_TRY(c, hipGetDeviceProperties(&prop, c->device));
-    char arch[64];
-    std::snprintf(arch, sizeof arch, "%.20s-%dcu", prop.gcnArchName, prop.multiProcessorCount);
-    const std::string key = tune_key(b, nu, arch);
-    auto cache = read_cache(cache_path);
-    auto hit = cache.find(key);
-    if (hit != cache.end()) {
-        b->tuning = {(int)hit->second[0], (int)hit->second[1], (int)hit->second[2], (int)hit->second[3]};
-        b->planned = false;
-        b->drop_graph();
-        return batch_plan(c, b, nu);
-    }
-    // candidates: grid mode at two strip groupings, queue mode with 1..3
-    // blocks per CU, sorted and natural order
-    const int nt = (nu->n1 + TILE - 1) / TILE;
-    std::vector<Tuning> cands;
-    for (int spb : {1, nt}) {
-        cands.push_back({0, 0, 0, spb});
-        for (int bpc : {1, 2, 3})
-            for (int sort : {1, 0}) cands.push_back({1, bpc, sort, spb});
-        if (nt == 1) break;
-    }
-    const bool prof = c->profiling;
-    c->profiling = true;
-    double best = 1e300;
-    Tuning best_t = b->tuning;
-    for (const Tuning& t : cands) {
-        b->tuning = t;
+    try {
+        if (!c) return ISRS_E_ARG;
+        if (!b) return fail(c, ISRS_E_ARG, "batch is null");
+        if (b->ctx != c) return fail(c, ISRS_E_ARG, "batch belongs to another context");
+        std::string m = validate_numerics_msg(nu);
+        if (!m.empty()) return fail(c, ISRS_E_ARG, m);
+        HIP_TRY(c, hipSetDevice(c->device));
+        hipDeviceProp_t prop;
+        HIP_TRY(c, hipGetDeviceProperties(&prop, c->device));
+        char arch[64];
+        std::snprintf(arch, sizeof arch, "%.20s-%dcu", prop.gcnArchName, prop.multiProcessorCount);
+        const std::string key = tune_key(b, nu, arch);
+        auto cache = read_cache(cache_path);
+        auto hit = cache.find(key);
+        if (hit != cache.end()) {
+            b->tuning = {(int)hit->second[0], (int)hit->second[1], (int)hit->second[2], (int)hit->second[3]};
+            b->planned = false;
+            b->drop_graph();
+            return batch_plan(c, b, nu);
+        }
+        // candidates: grid mode at two strip groupings, queue mode with 1..3
+        // blocks per CU, sorted and natural order
+        const int nt = (nu->n1 + TILE - 1) / TILE;
+        std::vector<Tuning> cands;
+        for (int spb : {1, nt}) {
+            cands.push_back({0, 0, 0, spb});
+            for (int bpc : {1, 2, 3})
+                for (int sort : {1, 0}) cands.push_back({1, bpc, sort, spb});
+            if (nt == 1) break;
+        }
+        const bool prof = c->profiling;
+        c->profiling = true;
+        double best = 1e300;
+        Tuning best_t = b->tuning;
+        for (const Tuning& t : cands) {
+            b->tuning = t;
+            b->planned = false;
+            int32_t rc = batch_plan(c, b, nu);
+            if (!rc) rc = batch_run(c, b, b->out.as<double>(), false);  // warm
+            if (!rc) rc = batch_run(c, b, b->out.as<double>(), false);
+            if (rc) {
+                c->profiling = prof;
+                return rc;
+            }
+            const double ms = c->stats.region_ms + c->stats.egn_ms;
+            if (ms < best) {
+                best = ms;
+                best_t = t;
+            }
+        }
+        c->profiling = prof;
+        b->tuning = best_t;
         b->planned = false;
         int32_t rc = batch_plan(c, b, nu);
-        if (!rc) rc = batch_run(c, b, b->out.as<double>(), false);  // warm
-        if (!rc) rc = batch_run(c, b, b->out.as<double>(), false);
-        if (rc) {
-            c->profiling = prof;
-            return rc;
-        }
-        const double ms = c->stats.region_ms + c->stats.egn_ms;
-        if (ms < best) {
-            best = ms;
-            best_t = t;
-        }
+        if (rc) return rc;
+        cache[key] = {(double)best_t.mode, (double)best_t.blocks_per_cu, (double)best_t.sort, (double)b->plan.spb, best};
+        if (!write_cache(cache_path, cache)) return fail(c, ISRS_E_ARG, "cannot write the autotune cache file");
+        return ISRS_OK;
+    } catch (...) {
+        return abi_exception(c);
     }
-    c->profiling = prof;
-    b->tuning = best_t;
-    b->planned = false;
-    int32_t rc = batch_plan(c, b, nu);
-    if (rc) return rc;
-    cache[key] = {(double)best_t.mode, (double)best_t.blocks_per_cu, (double)best_t.sort, (double)b->plan.spb, best};
-    if (!write_cache(cache_path, cache)) return fail(c, ISRS_E_ARG, "cannot write the autotune cache file");
-    return ISRS_OK;
 }
 
 }  // extern "C"

@@ -171,6 +171,7 @@ hipStream_t ctx_stream(isrs_ctx* c);
 int ctx_device(const isrs_ctx* c);
 int ctx_num_cu(const isrs_ctx* c);
 int32_t ctx_fail(isrs_ctx* c, int32_t code, const char* msg);
+int32_t abi_exception(isrs_ctx* c);   // inside a catch handler: status of the current exception
 
 // Evaluation of the context's link with the region kernel reading a residual
 // table (mu_method 2): before each launch chunk, fill() writes the table rows

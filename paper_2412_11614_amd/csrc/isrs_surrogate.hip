@@ -774,6 +774,14 @@ void dfree(void* p)
     if (p) (void)hipFree(p);
 }
 
+// frees and clears, so a failed reallocation never leaves a stale pointer
+template <typename T>
+void release(T*& p)
+{
+    dfree(p);
+    p = nullptr;
+}
+
 #define S_TRY(ctx, expr)                                                                                   \
     do {                                                                                                   \
         hipError_t _e = (expr);                                                                            \
@@ -814,18 +822,18 @@ int32_t refresh_bf16(isrs_ctx* c, isrs_surrogate::Member& m, hipStream_t st)
 int32_t ensure_batch(isrs_ctx* c, isrs_surrogate* s, int rows)
 {
     if (rows <= s->cap) return ISRS_OK;
-    dfree(s->xb);
+    release(s->xb);
     for (int l = 0; l < 4; ++l) {
-        dfree(s->Z[l]);
-        dfree(s->H[l]);
+        release(s->Z[l]);
+        release(s->H[l]);
     }
-    dfree(s->dZ);
-    dfree(s->dZh);
-    dfree(s->dZ2);
-    dfree(s->dZh2);
-    dfree(s->o);
-    dfree(s->dout);
-    dfree(s->loss_part);
+    release(s->dZ);
+    release(s->dZh);
+    release(s->dZ2);
+    release(s->dZh2);
+    release(s->o);
+    release(s->dout);
+    release(s->loss_part);
     s->cap = 0;
     S_TRY(c, dalloc(&s->xb, (size_t)rows * NIN));
     for (int l = 0; l < 4; ++l) {
@@ -894,8 +902,7 @@ void forward(isrs_surrogate* s, const isrs_surrogate::Member& m, const __bf16* x
 int32_t ensure_part(isrs_ctx* c, isrs_surrogate* s, size_t n)
 {
     if (n <= s->part_cap) return ISRS_OK;
-    dfree(s->part);
-    s->part = nullptr;
+    release(s->part);
     s->part_cap = 0;
     S_TRY(c, dalloc(&s->part, n));
     s->part_cap = n;
@@ -963,12 +970,12 @@ int32_t pack_rows(isrs_ctx* c, isrs_surrogate* s, const float* x, int64_t row0, 
 int32_t ensure_pred(isrs_ctx* c, isrs_surrogate* s, int64_t n)
 {
     if (n <= s->pcap) return ISRS_OK;
-    dfree(s->pred);
-    dfree(s->flag);
-    dfree(s->cnt);
-    dfree(s->off);
-    dfree(s->total);
-    dfree(s->idx);
+    release(s->pred);
+    release(s->flag);
+    release(s->cnt);
+    release(s->off);
+    release(s->total);
+    release(s->idx);
     s->pcap = 0;
     S_TRY(c, dalloc(&s->pred, (size_t)n * s->n_members));
     S_TRY(c, dalloc(&s->flag, (size_t)n));
@@ -1007,392 +1014,452 @@ extern "C" {
 
 int32_t isrs_surrogate_num_params(int64_t* n)
 {
-    if (!n) return ISRS_E_ARG;
-    *n = NP;
-    return ISRS_OK;
+    try {
+        if (!n) return ISRS_E_ARG;
+        *n = NP;
+        return ISRS_OK;
+    } catch (...) {
+        return abi_exception(nullptr);
+    }
 }
 
 int32_t isrs_surrogate_create(isrs_ctx* c, int32_t n_members, uint64_t seed, isrs_surrogate** out)
 {
-    if (!c) return ISRS_E_ARG;
-    if (!out || n_members < 1 || n_members > MAX_MEMBERS) return ctx_fail(c, ISRS_E_ARG, "1..16 members");
-    *out = nullptr;
-    isrs_surrogate* s = new (std::nothrow) isrs_surrogate();
-    if (!s) return ctx_fail(c, ISRS_E_NOMEM, "host allocation failed");
-    s->n_members = n_members;
-    s->seed = seed;
-    s->device = ctx_device(c);
-    S_TRY(c, hipSetDevice(s->device));
-    hipStream_t st = ctx_stream(c);
-    s->mem.resize(n_members);
-    std::vector<float> p;
-    for (int mi = 0; mi < n_members; ++mi) {
-        auto& m = s->mem[mi];
-        if (dalloc(&m.p, NP) != hipSuccess || dalloc(&m.m, NP) != hipSuccess || dalloc(&m.v, NP) != hipSuccess) {
-            isrs_surrogate_destroy(s);
-            return ctx_fail(c, ISRS_E_NOMEM, "device allocation failed");
-        }
-        for (int l = 0; l < 4; ++l) {
-            const size_t k = l == 0 ? NIN : NH;
-            if (dalloc(&m.wb[l], k * NH) != hipSuccess || dalloc(&m.wt[l], k * NH) != hipSuccess) {
-                isrs_surrogate_destroy(s);
-                return ctx_fail(c, ISRS_E_NOMEM, "device allocation failed");
+    try {
+        if (!c) return ISRS_E_ARG;
+        if (!out || n_members < 1 || n_members > MAX_MEMBERS) return ctx_fail(c, ISRS_E_ARG, "1..16 members");
+        *out = nullptr;
+        isrs_surrogate* s = new (std::nothrow) isrs_surrogate();
+        if (!s) return ctx_fail(c, ISRS_E_NOMEM, "host allocation failed");
+        s->n_members = n_members;
+        s->seed = seed;
+        s->device = ctx_device(c);
+        // every failure below releases what was allocated so far
+        auto setup = [&]() -> int32_t {
+            S_TRY(c, hipSetDevice(s->device));
+            hipStream_t st = ctx_stream(c);
+            s->mem.resize(n_members);
+            std::vector<float> p;
+            for (int mi = 0; mi < n_members; ++mi) {
+                auto& m = s->mem[mi];
+                S_TRY(c, dalloc(&m.p, NP));
+                S_TRY(c, dalloc(&m.m, NP));
+                S_TRY(c, dalloc(&m.v, NP));
+                for (int l = 0; l < 4; ++l) {
+                    const size_t k = l == 0 ? NIN : NH;
+                    S_TRY(c, dalloc(&m.wb[l], k * NH));
+                    S_TRY(c, dalloc(&m.wt[l], k * NH));
+                }
+                init_params(p, seed, mi);
+                S_TRY(c, hipMemcpy(m.p, p.data(), NP * sizeof(float), hipMemcpyHostToDevice));
+                S_TRY(c, hipMemset(m.m, 0, NP * sizeof(float)));
+                S_TRY(c, hipMemset(m.v, 0, NP * sizeof(float)));
+                int32_t rc = refresh_bf16(c, m, st);
+                if (rc) return rc;
             }
-        }
-        init_params(p, seed, mi);
-        S_TRY(c, hipMemcpy(m.p, p.data(), NP * sizeof(float), hipMemcpyHostToDevice));
-        S_TRY(c, hipMemset(m.m, 0, NP * sizeof(float)));
-        S_TRY(c, hipMemset(m.v, 0, NP * sizeof(float)));
-        int32_t rc = refresh_bf16(c, m, st);
+            S_TRY(c, dalloc(&s->grad, NP));
+            S_TRY(c, dalloc(&s->mom, 2));
+            S_TRY(c, hipStreamSynchronize(st));
+            return ISRS_OK;
+        };
+        const int32_t rc = setup();
         if (rc) {
             isrs_surrogate_destroy(s);
             return rc;
         }
+        *out = s;
+        return ISRS_OK;
+    } catch (...) {
+        return abi_exception(c);
     }
-    S_TRY(c, dalloc(&s->grad, NP));
-    S_TRY(c, dalloc(&s->mom, 2));
-    S_TRY(c, hipStreamSynchronize(st));
-    *out = s;
-    return ISRS_OK;
 }
 
 int32_t isrs_surrogate_destroy(isrs_surrogate* s)
 {
-    if (!s) return ISRS_E_ARG;
-    (void)hipSetDevice(s->device);
-    (void)hipDeviceSynchronize();
-    for (auto& m : s->mem) {
-        dfree(m.p);
-        dfree(m.m);
-        dfree(m.v);
-        for (int l = 0; l < 4; ++l) {
-            dfree(m.wb[l]);
-            dfree(m.wt[l]);
+    try {
+        if (!s) return ISRS_E_ARG;
+        (void)hipSetDevice(s->device);
+        (void)hipDeviceSynchronize();
+        for (auto& m : s->mem) {
+            dfree(m.p);
+            dfree(m.m);
+            dfree(m.v);
+            for (int l = 0; l < 4; ++l) {
+                dfree(m.wb[l]);
+                dfree(m.wt[l]);
+            }
         }
+        dfree(s->xb);
+        for (int l = 0; l < 4; ++l) {
+            dfree(s->Z[l]);
+            dfree(s->H[l]);
+        }
+        dfree(s->dZ);
+        dfree(s->dZh);
+        dfree(s->dZ2);
+        dfree(s->dZh2);
+        dfree(s->o);
+        dfree(s->dout);
+        dfree(s->loss_part);
+        dfree(s->grad);
+        dfree(s->mom);
+        dfree(s->part);
+        dfree(s->pred);
+        dfree(s->flag);
+        dfree(s->cnt);
+        dfree(s->off);
+        dfree(s->total);
+        dfree(s->idx);
+        dfree(s->qx);
+        dfree(s->qstate);
+        dfree(s->qcnt);
+        delete s;
+        return ISRS_OK;
+    } catch (...) {
+        return abi_exception(nullptr);
     }
-    dfree(s->xb);
-    for (int l = 0; l < 4; ++l) {
-        dfree(s->Z[l]);
-        dfree(s->H[l]);
-    }
-    dfree(s->dZ);
-    dfree(s->dZh);
-    dfree(s->dZ2);
-    dfree(s->dZh2);
-    dfree(s->o);
-    dfree(s->dout);
-    dfree(s->loss_part);
-    dfree(s->grad);
-    dfree(s->mom);
-    dfree(s->part);
-    dfree(s->pred);
-    dfree(s->flag);
-    dfree(s->cnt);
-    dfree(s->off);
-    dfree(s->total);
-    dfree(s->idx);
-    dfree(s->qx);
-    dfree(s->qstate);
-    dfree(s->qcnt);
-    delete s;
-    return ISRS_OK;
 }
 
 int32_t isrs_surrogate_datagen(isrs_ctx* c, int64_t n, uint64_t seed, float* x, float* r, float* y6)
 {
-    if (!c) return ISRS_E_ARG;
-    if (n < 1 || !x || !r) return ctx_fail(c, ISRS_E_ARG, "need n >= 1 and output buffers");
-    S_TRY(c, hipSetDevice(ctx_device(c)));
-    hipLaunchKernelGGL(datagen_kernel, dim3(blocks_for(n, 128)), dim3(128), 0, ctx_stream(c), n, mix64(seed), x,
-                       r, y6);
-    S_TRY(c, hipGetLastError());
-    return ISRS_OK;
+    try {
+        if (!c) return ISRS_E_ARG;
+        if (n < 1 || !x || !r) return ctx_fail(c, ISRS_E_ARG, "need n >= 1 and output buffers");
+        S_TRY(c, hipSetDevice(ctx_device(c)));
+        hipLaunchKernelGGL(datagen_kernel, dim3(blocks_for(n, 128)), dim3(128), 0, ctx_stream(c), n, mix64(seed), x,
+                           r, y6);
+        S_TRY(c, hipGetLastError());
+        return ISRS_OK;
+    } catch (...) {
+        return abi_exception(c);
+    }
 }
 
 int32_t isrs_closed_form_points(isrs_ctx* c, const float* x, int64_t n, float* y)
 {
-    if (!c) return ISRS_E_ARG;
-    if (n < 1 || !x || !y) return ctx_fail(c, ISRS_E_ARG, "need n >= 1 and buffers");
-    S_TRY(c, hipSetDevice(ctx_device(c)));
-    hipLaunchKernelGGL(closed_form_kernel, dim3(blocks_for(n, 128)), dim3(128), 0, ctx_stream(c), n, x, y);
-    S_TRY(c, hipGetLastError());
-    return ISRS_OK;
+    try {
+        if (!c) return ISRS_E_ARG;
+        if (n < 1 || !x || !y) return ctx_fail(c, ISRS_E_ARG, "need n >= 1 and buffers");
+        S_TRY(c, hipSetDevice(ctx_device(c)));
+        hipLaunchKernelGGL(closed_form_kernel, dim3(blocks_for(n, 128)), dim3(128), 0, ctx_stream(c), n, x, y);
+        S_TRY(c, hipGetLastError());
+        return ISRS_OK;
+    } catch (...) {
+        return abi_exception(c);
+    }
 }
 
 int32_t isrs_surrogate_train(isrs_ctx* c, isrs_surrogate* s, const float* x, const float* r, int64_t n,
                              const isrs_train_opts* o, double* loss_out)
 {
-    if (!c) return ISRS_E_ARG;
-    if (!s || !x || !r || !o) return ctx_fail(c, ISRS_E_ARG, "null argument");
-    if (o->batch < 64 || o->batch % 64 || o->batch > (1 << 20) || n < o->batch)
-        return ctx_fail(c, ISRS_E_ARG, "batch must be a positive multiple of 64, at most n and 2^20");
-    if (o->steps < 1 || !(o->lr > 0) || o->member < -1 || o->member >= s->n_members)
-        return ctx_fail(c, ISRS_E_ARG, "bad steps, lr or member");
-    S_TRY(c, hipSetDevice(s->device));
-    hipStream_t st = ctx_stream(c);
-    int32_t rc = ensure_batch(c, s, o->batch);
-    if (rc) return rc;
-    const int rows = o->batch;
-    const int lb = (int)blocks_for(rows, 4);
-    std::vector<float> lp(lb);
-    if (!s->scaled) {
-        hipLaunchKernelGGL(moments_kernel, dim3(1), dim3(1024), 0, st, n, r, 0, s->mom);
-        hipLaunchKernelGGL(moments_kernel, dim3(1), dim3(1024), 0, st, n, r, 1, s->mom);
-        double mo[2];
-        S_TRY(c, hipMemcpyAsync(mo, s->mom, sizeof mo, hipMemcpyDeviceToHost, st));
-        S_TRY(c, hipStreamSynchronize(st));
-        const double sd = std::sqrt(mo[1] / (double)n);
-        if (!std::isfinite(mo[0]) || !std::isfinite(sd)) return ctx_fail(c, ISRS_E_NUMERIC, "non-finite targets");
-        s->shift = mo[0];
-        s->scale = sd > 0.0 ? sd : 1.0;
-        s->scaled = 1;
-    }
-    for (int mi = 0; mi < s->n_members; ++mi) {
-        if (o->member >= 0 && mi != o->member) continue;
-        auto& m = s->mem[mi];
-        double tail = 0.0;
-        int tail_n = 0;
-        for (int it = 0; it < o->steps; ++it) {
-            // member mi walks the data from its own offset
-            const int64_t row0 = ((int64_t)(it + (int64_t)mi * 7919) * rows) % (n - rows + 1);
-            if ((rc = pack_rows(c, s, x, row0, rows, st))) return rc;
-            forward(s, m, s->xb, rows, true, s->o, false, st);
-            if ((rc = backward(c, s, m, r + row0, rows, st))) return rc;
-            m.step++;
-            const float c1 = 1.0f - std::pow(o->beta1, (float)m.step), c2 = 1.0f - std::pow(o->beta2, (float)m.step);
-            hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(NP, 256)), dim3(256), 0, st, (long)NP, m.p, s->grad, m.m,
-                               m.v, o->lr, o->beta1, o->beta2, o->eps, c1, c2);
-            if ((rc = refresh_bf16(c, m, st))) return rc;
-            if (it >= o->steps - 16) {
-                S_TRY(c, hipMemcpyAsync(lp.data(), s->loss_part, lb * sizeof(float), hipMemcpyDeviceToHost, st));
-                S_TRY(c, hipStreamSynchronize(st));
-                double e = 0.0;
-                for (float v : lp) e += v;
-                tail += e / rows * s->scale * s->scale;
-                tail_n++;
-            }
+    try {
+        if (!c) return ISRS_E_ARG;
+        if (!s || !x || !r || !o) return ctx_fail(c, ISRS_E_ARG, "null argument");
+        if (o->batch < 64 || o->batch % 64 || o->batch > (1 << 20) || n < o->batch)
+            return ctx_fail(c, ISRS_E_ARG, "batch must be a positive multiple of 64, at most n and 2^20");
+        if (o->steps < 1 || !(o->lr > 0) || o->member < -1 || o->member >= s->n_members)
+            return ctx_fail(c, ISRS_E_ARG, "bad steps, lr or member");
+        S_TRY(c, hipSetDevice(s->device));
+        hipStream_t st = ctx_stream(c);
+        int32_t rc = ensure_batch(c, s, o->batch);
+        if (rc) return rc;
+        const int rows = o->batch;
+        const int lb = (int)blocks_for(rows, 4);
+        std::vector<float> lp(lb);
+        if (!s->scaled) {
+            hipLaunchKernelGGL(moments_kernel, dim3(1), dim3(1024), 0, st, n, r, 0, s->mom);
+            hipLaunchKernelGGL(moments_kernel, dim3(1), dim3(1024), 0, st, n, r, 1, s->mom);
+            double mo[2];
+            S_TRY(c, hipMemcpyAsync(mo, s->mom, sizeof mo, hipMemcpyDeviceToHost, st));
+            S_TRY(c, hipStreamSynchronize(st));
+            const double sd = std::sqrt(mo[1] / (double)n);
+            if (!std::isfinite(mo[0]) || !std::isfinite(sd)) return ctx_fail(c, ISRS_E_NUMERIC, "non-finite targets");
+            s->shift = mo[0];
+            s->scale = sd > 0.0 ? sd : 1.0;
+            s->scaled = 1;
         }
-        if (loss_out) loss_out[mi] = tail / std::max(1, tail_n);
+        for (int mi = 0; mi < s->n_members; ++mi) {
+            if (o->member >= 0 && mi != o->member) continue;
+            auto& m = s->mem[mi];
+            double tail = 0.0;
+            int tail_n = 0;
+            for (int it = 0; it < o->steps; ++it) {
+                // member mi walks the data from its own offset
+                const int64_t row0 = ((int64_t)(it + (int64_t)mi * 7919) * rows) % (n - rows + 1);
+                if ((rc = pack_rows(c, s, x, row0, rows, st))) return rc;
+                forward(s, m, s->xb, rows, true, s->o, false, st);
+                if ((rc = backward(c, s, m, r + row0, rows, st))) return rc;
+                m.step++;
+                const float c1 = 1.0f - std::pow(o->beta1, (float)m.step), c2 = 1.0f - std::pow(o->beta2, (float)m.step);
+                hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(NP, 256)), dim3(256), 0, st, (long)NP, m.p, s->grad, m.m,
+                                   m.v, o->lr, o->beta1, o->beta2, o->eps, c1, c2);
+                if ((rc = refresh_bf16(c, m, st))) return rc;
+                if (it >= o->steps - 16) {
+                    S_TRY(c, hipMemcpyAsync(lp.data(), s->loss_part, lb * sizeof(float), hipMemcpyDeviceToHost, st));
+                    S_TRY(c, hipStreamSynchronize(st));
+                    double e = 0.0;
+                    for (float v : lp) e += v;
+                    tail += e / rows * s->scale * s->scale;
+                    tail_n++;
+                }
+            }
+            if (loss_out) loss_out[mi] = tail / std::max(1, tail_n);
+        }
+        S_TRY(c, hipStreamSynchronize(st));
+        return ISRS_OK;
+    } catch (...) {
+        return abi_exception(c);
     }
-    S_TRY(c, hipStreamSynchronize(st));
-    return ISRS_OK;
 }
 
 int32_t isrs_surrogate_grad(isrs_ctx* c, isrs_surrogate* s, int32_t member, const float* x, const float* r,
                             int64_t n, float* grads, double* loss)
 {
-    if (!c) return ISRS_E_ARG;
-    if (!s || !x || !r || !grads || member < 0 || member >= s->n_members || n < 64 || n % 64 || n > (1 << 20))
-        return ctx_fail(c, ISRS_E_ARG, "bad gradient request (rows: multiple of 64, at most 2^20)");
-    S_TRY(c, hipSetDevice(s->device));
-    hipStream_t st = ctx_stream(c);
-    const int rows = (int)n;
-    int32_t rc = ensure_batch(c, s, rows);
-    if (rc) return rc;
-    if ((rc = pack_rows(c, s, x, 0, rows, st))) return rc;
-    forward(s, s->mem[member], s->xb, rows, true, s->o, false, st);
-    if ((rc = backward(c, s, s->mem[member], r, rows, st))) return rc;
-    S_TRY(c, hipMemcpyAsync(grads, s->grad, NP * sizeof(float), hipMemcpyDeviceToHost, st));
-    const int lb = (int)blocks_for(rows, 4);
-    std::vector<float> lp(lb);
-    S_TRY(c, hipMemcpyAsync(lp.data(), s->loss_part, lb * sizeof(float), hipMemcpyDeviceToHost, st));
-    S_TRY(c, hipStreamSynchronize(st));
-    if (loss) {
-        double e = 0.0;
-        for (float v : lp) e += v;
-        *loss = e / rows;
+    try {
+        if (!c) return ISRS_E_ARG;
+        if (!s || !x || !r || !grads || member < 0 || member >= s->n_members || n < 64 || n % 64 || n > (1 << 20))
+            return ctx_fail(c, ISRS_E_ARG, "bad gradient request (rows: multiple of 64, at most 2^20)");
+        S_TRY(c, hipSetDevice(s->device));
+        hipStream_t st = ctx_stream(c);
+        const int rows = (int)n;
+        int32_t rc = ensure_batch(c, s, rows);
+        if (rc) return rc;
+        if ((rc = pack_rows(c, s, x, 0, rows, st))) return rc;
+        forward(s, s->mem[member], s->xb, rows, true, s->o, false, st);
+        if ((rc = backward(c, s, s->mem[member], r, rows, st))) return rc;
+        S_TRY(c, hipMemcpyAsync(grads, s->grad, NP * sizeof(float), hipMemcpyDeviceToHost, st));
+        const int lb = (int)blocks_for(rows, 4);
+        std::vector<float> lp(lb);
+        S_TRY(c, hipMemcpyAsync(lp.data(), s->loss_part, lb * sizeof(float), hipMemcpyDeviceToHost, st));
+        S_TRY(c, hipStreamSynchronize(st));
+        if (loss) {
+            double e = 0.0;
+            for (float v : lp) e += v;
+            *loss = e / rows;
+        }
+        return ISRS_OK;
+    } catch (...) {
+        return abi_exception(c);
     }
-    return ISRS_OK;
 }
 
 int32_t isrs_surrogate_predict(isrs_ctx* c, isrs_surrogate* s, const float* x, int64_t n, float* mean, float* spread)
 {
-    if (!c) return ISRS_E_ARG;
-    if (!s || !x || n < 1) return ctx_fail(c, ISRS_E_ARG, "null argument or n < 1");
-    S_TRY(c, hipSetDevice(s->device));
-    hipStream_t st = ctx_stream(c);
-    int32_t rc = predict_members(c, s, x, n, st);
-    if (rc) return rc;
-    hipLaunchKernelGGL(ensemble_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, s->n_members, s->pred, x, mean,
-                       spread, nullptr, 0.0, nullptr);
-    S_TRY(c, hipGetLastError());
-    return ISRS_OK;
+    try {
+        if (!c) return ISRS_E_ARG;
+        if (!s || !x || n < 1) return ctx_fail(c, ISRS_E_ARG, "null argument or n < 1");
+        S_TRY(c, hipSetDevice(s->device));
+        hipStream_t st = ctx_stream(c);
+        int32_t rc = predict_members(c, s, x, n, st);
+        if (rc) return rc;
+        hipLaunchKernelGGL(ensemble_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, s->n_members, s->pred, x, mean,
+                           spread, nullptr, 0.0, nullptr);
+        S_TRY(c, hipGetLastError());
+        return ISRS_OK;
+    } catch (...) {
+        return abi_exception(c);
+    }
 }
 
 int32_t isrs_surrogate_eval_points(isrs_ctx* c, isrs_surrogate* s, const float* x, int64_t n, double thr_db, float* y,
                                    int64_t* n_fallback)
 {
-    if (!c) return ISRS_E_ARG;
-    if (!s || !x || !y || n < 1 || n > (int64_t)1 << 31) return ctx_fail(c, ISRS_E_ARG, "bad query");
-    if (std::isnan(thr_db)) return ctx_fail(c, ISRS_E_ARG, "threshold is NaN");
-    S_TRY(c, hipSetDevice(s->device));
-    hipStream_t st = ctx_stream(c);
-    int32_t rc = predict_members(c, s, x, n, st);
-    if (rc) return rc;
-    // spread of ln|mu|^2 in dB of |mu|^2: 10 log10(e) per ln unit
-    const double thr_ln = thr_db < 0 ? -1.0 : thr_db / (10.0 / std::log(10.0));
-    hipLaunchKernelGGL(ensemble_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, s->n_members, s->pred, x,
-                       nullptr, nullptr, y, thr_ln, s->flag);
-    const int64_t nb = (n + CB - 1) / CB;
-    hipLaunchKernelGGL(count_kernel, dim3((unsigned)nb), dim3(CB), 0, st, n, s->flag, s->cnt);
-    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(64), 0, st, (int)nb, s->cnt, s->off, s->total);
-    hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)nb), dim3(CB), 0, st, n, s->flag, s->off, s->idx);
-    hipLaunchKernelGGL(fallback_kernel, dim3(blocks_for(n, 128)), dim3(128), 0, st, s->total, s->idx, x, y);
-    S_TRY(c, hipGetLastError());
-    if (n_fallback) {
-        int t = 0;
-        S_TRY(c, hipMemcpyAsync(&t, s->total, sizeof(int), hipMemcpyDeviceToHost, st));
-        S_TRY(c, hipStreamSynchronize(st));
-        *n_fallback = t;
+    try {
+        if (!c) return ISRS_E_ARG;
+        if (!s || !x || !y || n < 1 || n > (int64_t)1 << 31) return ctx_fail(c, ISRS_E_ARG, "bad query");
+        if (std::isnan(thr_db)) return ctx_fail(c, ISRS_E_ARG, "threshold is NaN");
+        S_TRY(c, hipSetDevice(s->device));
+        hipStream_t st = ctx_stream(c);
+        int32_t rc = predict_members(c, s, x, n, st);
+        if (rc) return rc;
+        // spread of ln|mu|^2 in dB of |mu|^2: 10 log10(e) per ln unit
+        const double thr_ln = thr_db < 0 ? -1.0 : thr_db / (10.0 / std::log(10.0));
+        hipLaunchKernelGGL(ensemble_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, s->n_members, s->pred, x,
+                           nullptr, nullptr, y, thr_ln, s->flag);
+        const int64_t nb = (n + CB - 1) / CB;
+        hipLaunchKernelGGL(count_kernel, dim3((unsigned)nb), dim3(CB), 0, st, n, s->flag, s->cnt);
+        hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(64), 0, st, (int)nb, s->cnt, s->off, s->total);
+        hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)nb), dim3(CB), 0, st, n, s->flag, s->off, s->idx);
+        hipLaunchKernelGGL(fallback_kernel, dim3(blocks_for(n, 128)), dim3(128), 0, st, s->total, s->idx, x, y);
+        S_TRY(c, hipGetLastError());
+        if (n_fallback) {
+            int t = 0;
+            S_TRY(c, hipMemcpyAsync(&t, s->total, sizeof(int), hipMemcpyDeviceToHost, st));
+            S_TRY(c, hipStreamSynchronize(st));
+            *n_fallback = t;
+        }
+        return ISRS_OK;
+    } catch (...) {
+        return abi_exception(c);
     }
-    return ISRS_OK;
 }
 
 int32_t isrs_surrogate_get_target_scale(const isrs_surrogate* s, double* shift, double* scale)
 {
-    if (!s || !shift || !scale) return ISRS_E_ARG;
-    *shift = s->shift;
-    *scale = s->scale;
-    return ISRS_OK;
+    try {
+        if (!s || !shift || !scale) return ISRS_E_ARG;
+        *shift = s->shift;
+        *scale = s->scale;
+        return ISRS_OK;
+    } catch (...) {
+        return abi_exception(nullptr);
+    }
 }
 
 int32_t isrs_surrogate_get_params(isrs_surrogate* s, int32_t member, float* p)
 {
-    if (!s || !p || member < 0 || member >= s->n_members) return ISRS_E_ARG;
-    if (hipSetDevice(s->device) != hipSuccess) return ISRS_E_DEVICE;
-    if (hipDeviceSynchronize() != hipSuccess) return ISRS_E_DEVICE;
-    if (hipMemcpy(p, s->mem[member].p, NP * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess) return ISRS_E_DEVICE;
-    return ISRS_OK;
+    try {
+        if (!s || !p || member < 0 || member >= s->n_members) return ISRS_E_ARG;
+        if (hipSetDevice(s->device) != hipSuccess) return ISRS_E_DEVICE;
+        if (hipDeviceSynchronize() != hipSuccess) return ISRS_E_DEVICE;
+        if (hipMemcpy(p, s->mem[member].p, NP * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess) return ISRS_E_DEVICE;
+        return ISRS_OK;
+    } catch (...) {
+        return abi_exception(nullptr);
+    }
 }
 
 int32_t isrs_surrogate_set_params(isrs_ctx* c, isrs_surrogate* s, int32_t member, const float* p)
 {
-    if (!c) return ISRS_E_ARG;
-    if (!s || !p || member < 0 || member >= s->n_members) return ctx_fail(c, ISRS_E_ARG, "bad member or params");
-    for (long i = 0; i < NP; ++i)
-        if (!std::isfinite(p[i])) return ctx_fail(c, ISRS_E_NUMERIC, "non-finite parameter");
-    S_TRY(c, hipSetDevice(s->device));
-    hipStream_t st = ctx_stream(c);
-    S_TRY(c, hipStreamSynchronize(st));
-    S_TRY(c, hipMemcpy(s->mem[member].p, p, NP * sizeof(float), hipMemcpyHostToDevice));
-    int32_t rc = refresh_bf16(c, s->mem[member], st);
-    if (rc) return rc;
-    S_TRY(c, hipStreamSynchronize(st));
-    return ISRS_OK;
+    try {
+        if (!c) return ISRS_E_ARG;
+        if (!s || !p || member < 0 || member >= s->n_members) return ctx_fail(c, ISRS_E_ARG, "bad member or params");
+        for (long i = 0; i < NP; ++i)
+            if (!std::isfinite(p[i])) return ctx_fail(c, ISRS_E_NUMERIC, "non-finite parameter");
+        S_TRY(c, hipSetDevice(s->device));
+        hipStream_t st = ctx_stream(c);
+        S_TRY(c, hipStreamSynchronize(st));
+        S_TRY(c, hipMemcpy(s->mem[member].p, p, NP * sizeof(float), hipMemcpyHostToDevice));
+        int32_t rc = refresh_bf16(c, s->mem[member], st);
+        if (rc) return rc;
+        S_TRY(c, hipStreamSynchronize(st));
+        return ISRS_OK;
+    } catch (...) {
+        return abi_exception(c);
+    }
 }
 
 int32_t isrs_surrogate_save(isrs_surrogate* s, const char* path)
 {
-    if (!s || !path) return ISRS_E_ARG;
-    if (hipSetDevice(s->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess) return ISRS_E_DEVICE;
-    std::ofstream f(path, std::ios::binary | std::ios::trunc);
-    if (!f) return ISRS_E_ARG;
-    const char magic[8] = {'I', 'S', 'R', 'S', 'S', 'U', 'R', '1'};
-    const int64_t hdr[4] = {s->n_members, (int64_t)s->seed, NP, s->scaled};
-    const double sc[2] = {s->shift, s->scale};
-    f.write(magic, 8);
-    f.write(reinterpret_cast<const char*>(hdr), sizeof hdr);
-    f.write(reinterpret_cast<const char*>(sc), sizeof sc);
-    std::vector<float> buf(NP);
-    for (auto& m : s->mem) {
-        f.write(reinterpret_cast<const char*>(&m.step), sizeof m.step);
-        for (float* d : {m.p, m.m, m.v}) {
-            if (hipMemcpy(buf.data(), d, NP * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess) return ISRS_E_DEVICE;
-            f.write(reinterpret_cast<const char*>(buf.data()), NP * sizeof(float));
+    try {
+        if (!s || !path) return ISRS_E_ARG;
+        if (hipSetDevice(s->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess) return ISRS_E_DEVICE;
+        std::ofstream f(path, std::ios::binary | std::ios::trunc);
+        if (!f) return ISRS_E_ARG;
+        const char magic[8] = {'I', 'S', 'R', 'S', 'S', 'U', 'R', '1'};
+        const int64_t hdr[4] = {s->n_members, (int64_t)s->seed, NP, s->scaled};
+        const double sc[2] = {s->shift, s->scale};
+        f.write(magic, 8);
+        f.write(reinterpret_cast<const char*>(hdr), sizeof hdr);
+        f.write(reinterpret_cast<const char*>(sc), sizeof sc);
+        std::vector<float> buf(NP);
+        for (auto& m : s->mem) {
+            f.write(reinterpret_cast<const char*>(&m.step), sizeof m.step);
+            for (float* d : {m.p, m.m, m.v}) {
+                if (hipMemcpy(buf.data(), d, NP * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess) return ISRS_E_DEVICE;
+                f.write(reinterpret_cast<const char*>(buf.data()), NP * sizeof(float));
+            }
         }
+        return f ? ISRS_OK : ISRS_E_ARG;
+    } catch (...) {
+        return abi_exception(nullptr);
     }
-    return f ? ISRS_OK : ISRS_E_ARG;
 }
 
 int32_t isrs_surrogate_load(isrs_ctx* c, isrs_surrogate* s, const char* path)
 {
-    if (!c) return ISRS_E_ARG;
-    if (!s || !path) return ctx_fail(c, ISRS_E_ARG, "null argument");
-    std::ifstream f(path, std::ios::binary);
-    if (!f) return ctx_fail(c, ISRS_E_ARG, "cannot open checkpoint");
-    char magic[8];
-    int64_t hdr[4];
-    double sc[2];
-    f.read(magic, 8);
-    f.read(reinterpret_cast<char*>(hdr), sizeof hdr);
-    f.read(reinterpret_cast<char*>(sc), sizeof sc);
-    if (!f || std::memcmp(magic, "ISRSSUR1", 8) != 0 || hdr[0] != s->n_members || hdr[2] != NP)
-        return ctx_fail(c, ISRS_E_ARG, "checkpoint does not match this surrogate");
-    S_TRY(c, hipSetDevice(s->device));
-    hipStream_t st = ctx_stream(c);
-    S_TRY(c, hipStreamSynchronize(st));
-    std::vector<float> buf(NP);
-    for (auto& m : s->mem) {
-        f.read(reinterpret_cast<char*>(&m.step), sizeof m.step);
-        for (float* d : {m.p, m.m, m.v}) {
-            f.read(reinterpret_cast<char*>(buf.data()), NP * sizeof(float));
-            if (!f) return ctx_fail(c, ISRS_E_ARG, "truncated checkpoint");
-            S_TRY(c, hipMemcpy(d, buf.data(), NP * sizeof(float), hipMemcpyHostToDevice));
+    try {
+        if (!c) return ISRS_E_ARG;
+        if (!s || !path) return ctx_fail(c, ISRS_E_ARG, "null argument");
+        std::ifstream f(path, std::ios::binary);
+        if (!f) return ctx_fail(c, ISRS_E_ARG, "cannot open checkpoint");
+        char magic[8];
+        int64_t hdr[4];
+        double sc[2];
+        f.read(magic, 8);
+        f.read(reinterpret_cast<char*>(hdr), sizeof hdr);
+        f.read(reinterpret_cast<char*>(sc), sizeof sc);
+        if (!f || std::memcmp(magic, "ISRSSUR1", 8) != 0 || hdr[0] != s->n_members || hdr[2] != NP)
+            return ctx_fail(c, ISRS_E_ARG, "checkpoint does not match this surrogate");
+        S_TRY(c, hipSetDevice(s->device));
+        hipStream_t st = ctx_stream(c);
+        S_TRY(c, hipStreamSynchronize(st));
+        std::vector<float> buf(NP);
+        for (auto& m : s->mem) {
+            f.read(reinterpret_cast<char*>(&m.step), sizeof m.step);
+            for (float* d : {m.p, m.m, m.v}) {
+                f.read(reinterpret_cast<char*>(buf.data()), NP * sizeof(float));
+                if (!f) return ctx_fail(c, ISRS_E_ARG, "truncated checkpoint");
+                S_TRY(c, hipMemcpy(d, buf.data(), NP * sizeof(float), hipMemcpyHostToDevice));
+            }
+            int32_t rc = refresh_bf16(c, m, st);
+            if (rc) return rc;
         }
-        int32_t rc = refresh_bf16(c, m, st);
-        if (rc) return rc;
+        s->seed = (uint64_t)hdr[1];
+        s->scaled = hdr[3];
+        s->shift = sc[0];
+        s->scale = sc[1];
+        S_TRY(c, hipStreamSynchronize(st));
+        return ISRS_OK;
+    } catch (...) {
+        return abi_exception(c);
     }
-    s->seed = (uint64_t)hdr[1];
-    s->scaled = hdr[3];
-    s->shift = sc[0];
-    s->scale = sc[1];
-    S_TRY(c, hipStreamSynchronize(st));
-    return ISRS_OK;
 }
 
 int32_t isrs_eval_eta_surrogate(isrs_ctx* c, isrs_surrogate* s, const isrs_numerics* nu, const int32_t* cuts,
                                 int32_t n_cut, double thr_db, double* eta, double* fallback_fraction)
 {
-    if (!c) return ISRS_E_ARG;
-    if (!s || !nu || !cuts || !eta) return ctx_fail(c, ISRS_E_ARG, "null argument");
-    if (std::isnan(thr_db)) return ctx_fail(c, ISRS_E_ARG, "threshold is NaN");
-    S_TRY(c, hipSetDevice(s->device));
-    struct Fill : SurrogateFill {
-        isrs_surrogate* s;
-        double thr_ln;
-        int64_t live = 0, fb = 0;
-        int32_t fill(isrs_ctx* c, const RegionArgs& ra, int item0, int item1, int n_sp, float* tab,
-                     hipStream_t st) override
-        {
-            const int64_t rows = (int64_t)(item1 - item0) * ra.N * ra.N * n_sp;
-            if (rows == 0) return ISRS_OK;
-            const unsigned nb = blocks_for(rows, 256);
-            if (rows > s->qcap) {
-                dfree(s->qx);
-                dfree(s->qstate);
-                dfree(s->qcnt);
-                s->qx = nullptr;
-                s->qstate = nullptr;
-                s->qcnt = nullptr;
-                s->qcap = 0;
-                S_TRY(c, dalloc(&s->qx, (size_t)rows * NIN));
-                S_TRY(c, dalloc(&s->qstate, (size_t)rows));
-                S_TRY(c, dalloc(&s->qcnt, 2 * (size_t)nb));
-                s->qcap = rows;
+    try {
+        if (!c) return ISRS_E_ARG;
+        if (!s || !nu || !cuts || !eta) return ctx_fail(c, ISRS_E_ARG, "null argument");
+        if (std::isnan(thr_db)) return ctx_fail(c, ISRS_E_ARG, "threshold is NaN");
+        S_TRY(c, hipSetDevice(s->device));
+        struct Fill : SurrogateFill {
+            isrs_surrogate* s;
+            double thr_ln;
+            int64_t live = 0, fb = 0;
+            int32_t fill(isrs_ctx* c, const RegionArgs& ra, int item0, int item1, int n_sp, float* tab,
+                         hipStream_t st) override
+            {
+                const int64_t rows = (int64_t)(item1 - item0) * ra.N * ra.N * n_sp;
+                if (rows == 0) return ISRS_OK;
+                const unsigned nb = blocks_for(rows, 256);
+                if (rows > s->qcap) {
+                    release(s->qx);
+                    release(s->qstate);
+                    release(s->qcnt);
+                    s->qcap = 0;
+                    S_TRY(c, dalloc(&s->qx, (size_t)rows * NIN));
+                    S_TRY(c, dalloc(&s->qstate, (size_t)rows));
+                    S_TRY(c, dalloc(&s->qcnt, 2 * (size_t)nb));
+                    s->qcap = rows;
+                }
+                hipLaunchKernelGGL(sur_query_kernel, dim3(nb), dim3(256), 0, st, ra, item0, rows, n_sp, s->qx, s->qstate);
+                S_TRY(c, hipGetLastError());
+                int32_t rc = predict_members(c, s, s->qx, rows, st);
+                if (rc) return rc;
+                hipLaunchKernelGGL(sur_combine_kernel, dim3(nb), dim3(256), 0, st, rows, s->n_members, s->pred,
+                                   s->qstate, thr_ln, tab, s->qcnt, s->qcnt + nb);
+                S_TRY(c, hipGetLastError());
+                std::vector<int> h(2 * (size_t)nb);
+                S_TRY(c, hipMemcpyAsync(h.data(), s->qcnt, h.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+                S_TRY(c, hipStreamSynchronize(st));
+                for (unsigned b = 0; b < nb; ++b) {
+                    live += h[b];
+                    fb += h[nb + b];
+                }
+                return ISRS_OK;
             }
-            hipLaunchKernelGGL(sur_query_kernel, dim3(nb), dim3(256), 0, st, ra, item0, rows, n_sp, s->qx, s->qstate);
-            S_TRY(c, hipGetLastError());
-            int32_t rc = predict_members(c, s, s->qx, rows, st);
-            if (rc) return rc;
-            hipLaunchKernelGGL(sur_combine_kernel, dim3(nb), dim3(256), 0, st, rows, s->n_members, s->pred,
-                               s->qstate, thr_ln, tab, s->qcnt, s->qcnt + nb);
-            S_TRY(c, hipGetLastError());
-            std::vector<int> h(2 * (size_t)nb);
-            S_TRY(c, hipMemcpyAsync(h.data(), s->qcnt, h.size() * sizeof(int), hipMemcpyDeviceToHost, st));
-            S_TRY(c, hipStreamSynchronize(st));
-            for (unsigned b = 0; b < nb; ++b) {
-                live += h[b];
-                fb += h[nb + b];
-            }
-            return ISRS_OK;
-        }
-    } f;
-    f.s = s;
-    f.thr_ln = thr_db < 0 ? -1.0 : thr_db / (10.0 / std::log(10.0));
-    int32_t rc = eval_eta_table(c, nu, cuts, n_cut, f, eta);
-    if (rc) return rc;
-    if (fallback_fraction) *fallback_fraction = f.live > 0 ? (double)f.fb / (double)f.live : 0.0;
-    return ISRS_OK;
+        } f;
+        f.s = s;
+        f.thr_ln = thr_db < 0 ? -1.0 : thr_db / (10.0 / std::log(10.0));
+        int32_t rc = eval_eta_table(c, nu, cuts, n_cut, f, eta);
+        if (rc) return rc;
+        if (fallback_fraction) *fallback_fraction = f.live > 0 ? (double)f.fb / (double)f.live : 0.0;
+        return ISRS_OK;
+    } catch (...) {
+        return abi_exception(c);
+    }
 }
 
 }  // extern "C"
