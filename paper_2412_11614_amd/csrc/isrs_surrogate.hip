@@ -51,6 +51,7 @@ constexpr int MAX_MEMBERS = 16;
 constexpr int KSPLIT_ROWS = 512;         // batch rows per split of a weight-gradient product
 
 typedef __attribute__((ext_vector_type(8))) __bf16 bf8;
+typedef __attribute__((ext_vector_type(4))) __bf16 bf4;
 typedef __attribute__((ext_vector_type(16))) float f16v;
 
 // Feature box (physical units), scaled linearly to [-1, 1].
@@ -221,7 +222,13 @@ struct GemmArgs {
     const float* Zin;  // EPI_DSILU: pre-activation at (m, n), ldc layout
 };
 
-__device__ __forceinline__ float sigm(float z) { return 1.0f / (1.0f + __expf(-z)); }
+// logistic function with the hardware base-2 exponential and reciprocal (1 ulp
+// each; activations are stored in BF16): 1 / (1 + 2^(-z log2 e)), exact limits
+// 0 and 1 for large |z|
+__device__ __forceinline__ float sigm(float z)
+{
+    return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-z * 1.44269504088896341f));
+}
 
 template <int EPI>
 __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
@@ -324,29 +331,30 @@ constexpr int FB_M = 128;
 constexpr int LDH = NH + 8;
 constexpr int LDX = NIN + 8;
 
-// acc[rt][ct] = rows 32 rt .. + 31 of src times W columns 64 w + 32 ct .. + 31,
-// over K (a compile-time count, fully unrolled so weight loads issue early).
+// acc[ft][rt]: output features 64 w + 32 ft .. + 31 (rows of the MFMA tile)
+// for data rows 32 rt .. + 31 (its columns), i.e. (x W)^T = W^T x^T over K (a
+// compile-time count, fully unrolled).  A operand: W^T rows (16 bytes along k,
+// from L2); B operand: activation rows of the tile (16 bytes along k, LDS).
 template <int K, int LD>
 __device__ __forceinline__ void fused_products(const __bf16* src, const __bf16* Wt, int w, int lr, int kh,
-                                               f16v (&acc)[4][2])
+                                               f16v (&acc)[2][4])
 {
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt) {
-        acc[rt][0] = f16v{};
-        acc[rt][1] = f16v{};
-    }
+    for (int ft = 0; ft < 2; ++ft)
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) acc[ft][rt] = f16v{};
 #pragma unroll
     for (int ks = 0; ks < K / 16; ++ks) {
         const int kk = 16 * ks + kh;
-        bf8 bv[2];
+        bf8 av[2];
 #pragma unroll
-        for (int ct = 0; ct < 2; ++ct) bv[ct] = *reinterpret_cast<const bf8*>(Wt + (size_t)(64 * w + 32 * ct + lr) * K + kk);
+        for (int ft = 0; ft < 2; ++ft) av[ft] = *reinterpret_cast<const bf8*>(Wt + (size_t)(64 * w + 32 * ft + lr) * K + kk);
 #pragma unroll
         for (int rt = 0; rt < 4; ++rt) {
-            const bf8 av = *reinterpret_cast<const bf8*>(src + (32 * rt + lr) * LD + kk);
+            const bf8 bv = *reinterpret_cast<const bf8*>(src + (32 * rt + lr) * LD + kk);
 #pragma unroll
-            for (int ct = 0; ct < 2; ++ct)
-                acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv[ct], acc[rt][ct], 0, 0, 0);
+            for (int ft = 0; ft < 2; ++ft)
+                acc[ft][rt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[ft], bv, acc[ft][rt], 0, 0, 0);
         }
     }
 }
@@ -385,24 +393,33 @@ __global__ void __launch_bounds__(256, 2) mlp_fused_kernel(FusedArgs a)
         for (int l = 0; l < 4; ++l) {
             const __bf16* src = l == 0 ? Xs : Hs;
             const __bf16* Wt = a.wt[m][l];
-            f16v acc[4][2];
+            f16v acc[2][4];
             if (l == 0)
                 fused_products<NIN, LDX>(src, Wt, w, lr, kh, acc);
             else
                 fused_products<NH, LDH>(src, Wt, w, lr, kh, acc);
             __syncthreads();  // every wave has read the layer's input
+            // register 4 g + e of tile (ft, rt) holds feature 64 w + 32 ft + 8 g + 4 (lane / 32) + e
+            // of data row 32 rt + lane % 32: four consecutive features, one 8-byte write
             const float* bias = pm + B_OFF[l];
-            const float bc[2] = {bias[64 * w + lr], bias[64 * w + 32 + lr]};
 #pragma unroll
-            for (int rt = 0; rt < 4; ++rt)
+            for (int ft = 0; ft < 2; ++ft)
 #pragma unroll
-                for (int ct = 0; ct < 2; ++ct)
+                for (int g = 0; g < 4; ++g) {
+                    const int f0 = 64 * w + 32 * ft + 8 * g + 4 * (lane >> 5);
+                    const float4 bq = *reinterpret_cast<const float4*>(bias + f0);
+                    const float bb[4] = {bq.x, bq.y, bq.z, bq.w};
 #pragma unroll
-                    for (int r = 0; r < 16; ++r) {
-                        const int row = 32 * rt + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                        const float z = acc[rt][ct][r] + bc[ct];
-                        Hs[row * LDH + 64 * w + 32 * ct + lr] = (__bf16)(z * sigm(z));
+                    for (int rt = 0; rt < 4; ++rt) {
+                        bf4 hv;
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const float z = acc[ft][rt][4 * g + e] + bb[e];
+                            hv[e] = (__bf16)(z * sigm(z));
+                        }
+                        *reinterpret_cast<bf4*>(Hs + (32 * rt + lr) * LDH + f0) = hv;
                     }
+                }
             __syncthreads();
         }
         // output layer: two threads per row, 128 columns each
