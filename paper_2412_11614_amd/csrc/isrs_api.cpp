@@ -437,6 +437,18 @@ void plan_link_work(const LinkInput& L, int link, const isrs_numerics* nu, const
         steps_per_point += p.spans[d.span0 + s].K;
     }
     const double unit_cost = (double)steps_per_point + 15.0 * d.n_sp;
+    // square list of one instance: explicit pairs, or every pair of active
+    // channels with k1 <= k2 (f1 <-> f2 symmetry: the mirror is folded in)
+    std::vector<std::pair<int, int>> pairs;
+    if (explicit_sq) {
+        for (int t = 0; t < m_explicit; ++t) pairs.emplace_back(kappa12[2 * t], kappa12[2 * t + 1]);
+    } else {
+        std::vector<int> act;
+        for (int k = 0; k < nc; ++k)
+            if (L.power[k] > 0) act.push_back(k);
+        for (size_t i = 0; i < act.size(); ++i)
+            for (size_t j = i; j < act.size(); ++j) pairs.emplace_back(act[i], act[j]);
+    }
     for (int q = 0; q < L.n_cut; ++q) {
         const int cut = L.cuts[q];
         for (int n = 0; n < p.n_f; ++n) {
@@ -449,19 +461,9 @@ void plan_link_work(const LinkInput& L, int link, const isrs_numerics* nu, const
             const int* lp = &p.livep[d.livep0 + (size_t)n * 3 * (AD + 1)];
             int any_live[3];
             for (int l = 0; l < 3; ++l) any_live[l] = lp[l * (AD + 1) + AD] > 0;
-            const int n_sq = explicit_sq ? m_explicit : nc * nc;
-            for (int t = 0; t < n_sq; ++t) {
-                int k1, k2;
-                if (explicit_sq) {
-                    k1 = kappa12[2 * t];
-                    k2 = kappa12[2 * t + 1];
-                } else {
-                    k1 = t / nc;
-                    k2 = t % nc;
-                    if (k2 < k1) continue;  // f1 <-> f2 symmetry: the mirror is folded in
-                }
+            for (const auto& pr : pairs) {
+                const int k1 = pr.first, k2 = pr.second;
                 const bool pair_active = L.power[k1] > 0 && L.power[k2] > 0;
-                if (!pair_active && !explicit_sq) continue;
                 SquareItem it{};
                 it.inst = (int)p.insts.size();
                 it.k1 = k1;
@@ -541,11 +543,23 @@ void plan_finish(Plan& p, size_t ycap, const Tuning& tu, int max_items = 0)
     p.order.resize(n_units);
     std::iota(p.order.begin(), p.order.end(), 0);
     if (tu.mode == 1 && tu.sort) {
+        // stable bucket sort on a cost class (1/64 octave): the queue only needs
+        // the longest units first, and the order stays deterministic
+        constexpr int NB = 4096;
+        std::vector<uint16_t> cls(p.items.size());
+        for (size_t i = 0; i < p.items.size(); ++i) {
+            const double lc = 64.0 * std::log2(std::max(1.0, p.item_cost[i]));
+            cls[i] = (uint16_t)(NB - 1 - std::min<double>(NB - 1, std::floor(lc)));
+        }
+        std::vector<int> tmp;
         for (size_t ch = 0; ch + 1 < p.chunk_begin.size(); ++ch) {
             const size_t b = (size_t)p.chunk_begin[ch] * p.n_groups, e = (size_t)p.chunk_begin[ch + 1] * p.n_groups;
-            std::stable_sort(p.order.begin() + b, p.order.begin() + e, [&](int x, int y) {
-                return p.item_cost[x / p.n_groups] > p.item_cost[y / p.n_groups];
-            });
+            std::vector<size_t> start(NB + 1, 0);
+            for (size_t u = b; u < e; ++u) start[cls[u / p.n_groups] + 1]++;
+            for (int k = 0; k < NB; ++k) start[k + 1] += start[k];
+            tmp.resize(e - b);
+            for (size_t u = b; u < e; ++u) tmp[start[cls[u / p.n_groups]]++] = (int)u;
+            std::copy(tmp.begin(), tmp.end(), p.order.begin() + b);
         }
     }
 }
@@ -1007,6 +1021,15 @@ int32_t batch_plan(isrs_ctx* c, isrs_batch* b, const isrs_numerics* nu)
     Plan p;
     try {
         plan_begin(nu, p);
+        size_t est = 0;
+        for (int l = 0; l < b->n_links; ++l) {
+            const LinkInput L = b->link(l);
+            size_t act = 0;
+            for (int k = 0; k < L.n_ch; ++k) act += L.power[k] > 0;
+            est += (size_t)L.n_cut * p.n_f * act * (act + 1) / 2;
+        }
+        p.items.reserve(est);
+        p.item_cost.reserve(est);
         for (int l = 0; l < b->n_links; ++l) plan_link_tables(b->link(l), nu, p);
         for (int l = 0; l < b->n_links; ++l) plan_link_work(b->link(l), l, nu, nullptr, 0, p);
         plan_finish(p, c->ycap, b->tuning);
