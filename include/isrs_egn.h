@@ -307,6 +307,16 @@ int32_t isrs_surrogate_destroy(isrs_surrogate* sur);
 int32_t isrs_surrogate_datagen(isrs_ctx* ctx, int64_t n, uint64_t seed, float* x_dev, float* r_dev,
                                float* y6_dev);
 
+/* As isrs_surrogate_datagen, with the query points drawn from the links of a
+ * batch: a link, one of its CUTs, a pair of its active channels, a point of
+ * the n_grid x n_grid square lying on a live island, and a span, each
+ * uniform (SplitMix64 counters keyed by seed); f is the CUT centre.  Draws
+ * outside the sampling box (or from links whose B_tot is not 10 THz) are
+ * redrawn and counted in n_rejected (host, nullable).  Fails with
+ * ISRS_E_ARG when 4096 draws in a row are rejected. */
+int32_t isrs_surrogate_datagen_batch(isrs_ctx* ctx, const isrs_batch* batch, int32_t n_grid, int64_t n,
+                                     uint64_t seed, float* x_dev, float* r_dev, float* y6_dev, int64_t* n_rejected);
+
 /* Adam on the mean squared error of the normalised residual
  * t = (r - shift) / scale for opts->steps minibatches per member (rows drawn
  * in order, wrapping).  shift and scale are the mean and standard deviation

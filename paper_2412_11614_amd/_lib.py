@@ -39,7 +39,7 @@ EXPORTED = [
     "isrs_surrogate_predict", "isrs_surrogate_eval_points", "isrs_closed_form_points",
     "isrs_surrogate_num_params", "isrs_surrogate_get_params", "isrs_surrogate_set_params",
     "isrs_surrogate_grad", "isrs_surrogate_save", "isrs_surrogate_load", "isrs_surrogate_get_target_scale",
-    "isrs_eval_eta_surrogate", "isrs_eval_eta_dz", "isrs_choose_dz",
+    "isrs_eval_eta_surrogate", "isrs_eval_eta_dz", "isrs_choose_dz", "isrs_surrogate_datagen_batch",
 ]
 
 SUR_FEATURES = 16
@@ -146,6 +146,8 @@ def lib():
     L.isrs_surrogate_save.argtypes = [vp, C.c_char_p]
     L.isrs_surrogate_load.argtypes = [vp, vp, C.c_char_p]
     L.isrs_surrogate_get_target_scale.argtypes = [vp, dp, dp]
+    L.isrs_surrogate_datagen_batch.argtypes = [vp, vp, C.c_int32, C.c_int64, C.c_uint64, vp, vp, vp,
+                                               C.POINTER(C.c_int64)]
     L.isrs_eval_eta_dz.argtypes = [vp, C.POINTER(Numerics_c), ip, C.c_int32, dp, dp, dp, dp]
     L.isrs_choose_dz.argtypes = [vp, C.POINTER(Numerics_c), ip, C.c_int32, dp, C.c_int32, C.c_double, dp, dp]
     L.isrs_eval_eta_surrogate.argtypes = [vp, vp, C.POINTER(Numerics_c), ip, C.c_int32, C.c_double, dp, dp]
@@ -565,6 +567,16 @@ class Engine:
         n = r.numel()
         self._check(self._L.isrs_surrogate_datagen(self._h, n, int(seed), _dev(x, "torch.float32", 16 * n),
                                                    _dev(r, "torch.float32", n), _dev(y6, "torch.float32", n)))
+
+    def surrogate_datagen_batch(self, batch, n_grid, x, r, seed, y6=None):
+        """Fills x [n, 16], r [n] (and y6) with query points drawn from the links
+        of a Batch; returns the number of draws rejected as outside the box."""
+        n = r.numel()
+        rej = C.c_int64()
+        self._check(self._L.isrs_surrogate_datagen_batch(self._h, batch._h, int(n_grid), n, int(seed),
+                                                         _dev(x, "torch.float32", 16 * n), _dev(r, "torch.float32", n),
+                                                         _dev(y6, "torch.float32", n), C.byref(rej)))
+        return int(rej.value)
 
     def closed_form_points(self, x, y):
         n = x.numel() // SUR_FEATURES

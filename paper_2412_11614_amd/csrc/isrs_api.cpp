@@ -1147,6 +1147,14 @@ int ctx_device(const isrs_ctx* c) { return c->device; }
 int ctx_num_cu(const isrs_ctx* c) { return c->n_cu; }
 int32_t ctx_fail(isrs_ctx* c, int32_t code, const char* msg) { return fail(c, code, msg); }
 
+int batch_num_links(const isrs_batch* b) { return b ? b->n_links : 0; }
+
+LinkView batch_link_view(const isrs_batch* b, int link)
+{
+    const LinkInput L = b->link(link);
+    return {L.n_ch, L.spacing, L.rs, L.rolloff, L.power, L.spans, L.n_sp, L.cuts, L.n_cut};
+}
+
 int32_t eval_eta_table(isrs_ctx* c, const isrs_numerics* nu, const int32_t* cuts, int n_cut, SurrogateFill& sf,
                        double* eta_host)
 {

@@ -182,6 +182,19 @@ struct SurrogateFill {
                          hipStream_t st) = 0;
 };
 constexpr int64_t SUR_TAB_ROWS = int64_t(1) << 25;  // table rows per launch chunk
+
+// Read-only view of one link of a batch (host arrays owned by the batch).
+struct LinkView {
+    int n_ch;
+    double spacing, rs, rolloff;
+    const double* power;
+    const isrs_span* spans;
+    int n_sp;
+    const int32_t* cuts;
+    int n_cut;
+};
+int batch_num_links(const isrs_batch* b);
+LinkView batch_link_view(const isrs_batch* b, int link);
 int32_t eval_eta_table(isrs_ctx* c, const isrs_numerics* nu, const int32_t* cuts, int n_cut, SurrogateFill& sf,
                        double* eta_host);
 }  // namespace isrs

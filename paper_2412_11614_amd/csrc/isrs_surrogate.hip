@@ -54,9 +54,14 @@ typedef __attribute__((ext_vector_type(8))) __bf16 bf8;
 typedef __attribute__((ext_vector_type(4))) __bf16 bf4;
 typedef __attribute__((ext_vector_type(16))) float f16v;
 
-// Feature box (physical units), scaled linearly to [-1, 1].
-__constant__ double c_lo[NF] = {-5.0, -5.0, -5.0, 80.0, 0.18, -23.0, 0.10, 0.020, 17.0};
-__constant__ double c_hi[NF] = {5.0, 5.0, 5.0, 100.0, 0.22, -20.0, 0.16, 0.035, 23.0};
+// Feature box (physical units), scaled linearly to [-1, 1]; B_tot of Eq. 25.
+#define BOX_LO {-5.0, -5.0, -5.0, 80.0, 0.18, -23.0, 0.10, 0.020, 17.0}
+#define BOX_HI {5.0, 5.0, 5.0, 100.0, 0.22, -20.0, 0.16, 0.035, 23.0}
+__constant__ double c_lo[NF] = BOX_LO;
+__constant__ double c_hi[NF] = BOX_HI;
+constexpr double h_lo[NF] = BOX_LO;
+constexpr double h_hi[NF] = BOX_HI;
+constexpr double BOX_BTOT = 10.0;
 
 // ---------------------------------------------------------------------------
 // Counter-based generator (SplitMix64 finaliser, S. Vigna): u = mix(key, i).
@@ -189,6 +194,17 @@ __global__ void datagen_kernel(int64_t n, uint64_t key, float* x, float* r, floa
     for (int j = 0; j < NIN; ++j) x[i * NIN + j] = xs[j];
     double y, y6;
     closed_form(decode(xs), &y, &y6);
+    r[i] = (float)(y - y6);
+    if (y6o) y6o[i] = (float)y6;
+}
+
+// Labels of given query points: r = y - y6 and y6 (closed form, FP64).
+__global__ void label_kernel(int64_t n, const float* x, float* r, float* y6o)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double y, y6;
+    closed_form(decode(x + i * NIN), &y, &y6);
     r[i] = (float)(y - y6);
     if (y6o) y6o[i] = (float)y6;
 }
@@ -1146,6 +1162,81 @@ int32_t isrs_surrogate_datagen(isrs_ctx* c, int64_t n, uint64_t seed, float* x, 
         hipLaunchKernelGGL(datagen_kernel, dim3(blocks_for(n, 128)), dim3(128), 0, ctx_stream(c), n, mix64(seed), x,
                            r, y6);
         S_TRY(c, hipGetLastError());
+        return ISRS_OK;
+    } catch (...) {
+        return abi_exception(c);
+    }
+}
+
+int32_t isrs_surrogate_datagen_batch(isrs_ctx* c, const isrs_batch* b, int32_t n_grid, int64_t n, uint64_t seed,
+                                     float* x, float* r, float* y6, int64_t* n_rejected)
+{
+    try {
+        if (!c) return ISRS_E_ARG;
+        if (!b || n < 1 || !x || !r || n_grid < 1) return ctx_fail(c, ISRS_E_ARG, "need a batch, n >= 1, n_grid >= 1 and outputs");
+        const int nl = batch_num_links(b);
+        std::vector<LinkView> links(nl);
+        std::vector<std::vector<int>> act(nl);
+        std::vector<double> pdbm(nl);
+        for (int l = 0; l < nl; ++l) {
+            links[l] = batch_link_view(b, l);
+            double pt = 0.0;
+            for (int k = 0; k < links[l].n_ch; ++k)
+                if (links[l].power[k] > 0) {
+                    act[l].push_back(k);
+                    pt += links[l].power[k];
+                }
+            pdbm[l] = 10.0 * std::log10(pt / 1e-3);
+        }
+        const uint64_t key = mix64(seed ^ 0x6c696e6b73ull);
+        uint64_t ctr = 0;
+        auto u = [&]() { return u01(key, ctr++); };
+        auto pick = [&](int m) { return std::min(m - 1, (int)(u() * m)); };
+        std::vector<float> hx((size_t)n * NIN, 0.0f);
+        int64_t rejected = 0;
+        for (int64_t q = 0; q < n; ++q) {
+            bool done = false;
+            for (int tr = 0; tr < 4096 && !done; ++tr) {
+                const int l = pick(nl);
+                const LinkView& L = links[l];
+                if (L.n_cut < 1 || act[l].empty()) continue;
+                const int cut = L.cuts[pick(L.n_cut)];
+                const int k1 = act[l][pick((int)act[l].size())], k2 = act[l][pick((int)act[l].size())];
+                const int i = pick(n_grid), j = pick(n_grid), s_ = pick(L.n_sp);
+                const double W = (1.0 + L.rolloff) * L.rs, h = W / n_grid, df = L.spacing;
+                const double f1 = (i + 0.5 - 0.5 * n_grid) * h, f2 = (j + 0.5 - 0.5 * n_grid) * h;
+                bool island = false;
+                for (int li = -1; li <= 1; ++li) {
+                    const int k3 = k1 + k2 - cut + li;
+                    if (k3 >= 0 && k3 < L.n_ch && L.power[k3] > 0 && std::fabs(f1 + f2 - li * df) <= 0.5 * W) island = true;
+                }
+                if (!island) continue;
+                const double hg = 0.5 * (L.n_ch - 1);
+                const isrs_span& sp = L.spans[s_];
+                const double ph[NF] = {(k1 - hg) * df + f1, (k2 - hg) * df + f2, (cut - hg) * df, sp.length_km,
+                                       sp.alpha_db_km, sp.beta2_ps2_km, sp.beta3_ps3_km, sp.cr_w_km_thz, pdbm[l]};
+                bool inbox = std::fabs(L.n_ch * df - BOX_BTOT) <= 1e-9;
+                float* xr = hx.data() + (size_t)q * NIN;
+                for (int f = 0; f < NF; ++f) {
+                    const double v = 2.0 * (ph[f] - h_lo[f]) / (h_hi[f] - h_lo[f]) - 1.0;
+                    if (!(std::fabs(v) <= 1.0)) inbox = false;
+                    xr[f] = (float)v;
+                }
+                if (!inbox) {
+                    ++rejected;
+                    continue;
+                }
+                done = true;
+            }
+            if (!done) return ctx_fail(c, ISRS_E_ARG, "the batch has no query points inside the sampling box");
+        }
+        S_TRY(c, hipSetDevice(ctx_device(c)));
+        hipStream_t st = ctx_stream(c);
+        S_TRY(c, hipMemcpyAsync(x, hx.data(), hx.size() * sizeof(float), hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(label_kernel, dim3(blocks_for(n, 128)), dim3(128), 0, st, n, x, r, y6);
+        S_TRY(c, hipGetLastError());
+        S_TRY(c, hipStreamSynchronize(st));   // the host rows are released on return
+        if (n_rejected) *n_rejected = rejected;
         return ISRS_OK;
     } catch (...) {
         return abi_exception(c);

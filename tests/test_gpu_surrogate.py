@@ -257,3 +257,35 @@ def test_eta_with_surrogate_in_box(engine, data):
     assert np.max(np.abs(err_inf)) < 0.5
     assert np.max(np.abs(err_01)) <= np.max(np.abs(err_inf)) + 1e-3
     s.close()
+
+
+def test_datagen_from_links(engine):
+    """Query points drawn from the links of a batch: labels match the oracle,
+    points lie on live islands of the drawn links, draws outside the box are
+    rejected, and a batch with no in-box point is an error."""
+    import torch
+    from paper_2412_11614_amd import _lib, workloads as W
+    links = [W.cl_100ch_10span(n_grid=16), W.small_mixed(seed=61, n_ch=5, n_spans=2, n_grid=16)]
+    b = engine.batch(links)
+    n = 4096
+    x = torch.empty(n, 16, device="cuda")
+    r = torch.empty(n, device="cuda")
+    y6 = torch.empty(n, device="cuda")
+    rej = engine.surrogate_datagen_batch(b, 64, x, r, seed=5, y6=y6)
+    assert rej > 0                      # the small link is outside the box (B_tot != 10 THz)
+    xs, rs, y6s = x.cpu().numpy(), r.cpu().numpy(), y6.cpu().numpy()
+    assert np.all(np.abs(xs[:, :S.NF]) <= 1.0)
+    phys = S.decode(xs)
+    spans = links[0].link.spans
+    # every point carries one of the first link's spans
+    assert np.all(np.min(np.abs(phys[:, 3][:, None] - spans["length_km"][None, :]), axis=1) < 1e-4)
+    rng = np.random.default_rng(1)
+    for i in rng.choice(n, size=16, replace=False):
+        y_ref, y6_ref = S.target(phys[i])
+        assert abs(rs[i] - (y_ref - y6_ref)) <= 2e-6 * max(1.0, abs(y_ref))
+        assert abs(y6s[i] - y6_ref) <= 2e-6 * max(1.0, abs(y6_ref))
+    b.close()
+    b2 = engine.batch([links[1]])
+    with pytest.raises(_lib.IsrsError):
+        engine.surrogate_datagen_batch(b2, 64, x[:16].contiguous(), r[:16].contiguous(), seed=1)
+    b2.close()
