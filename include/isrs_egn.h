@@ -247,16 +247,16 @@ int32_t isrs_batch_eval_dev(isrs_ctx* ctx, isrs_batch* batch, const isrs_numeric
 
 /* Launch-shape autotuner: times the candidate region launches (one block per
  * work unit, or persistent blocks per CU in {1, 2, 3} on the queue; natural
- * or cost-sorted order; strip grouping) on this batch, keeps the fastest for
+ * or cost-sorted order; slice grouping) on this batch, keeps the fastest for
  * the batch, and caches the choice in the JSON file at cache_path (nullable)
  * keyed by architecture, grid size, segment-count and span-count buckets,
  * precision and FWM form.  A cached entry is reused without timing. */
 int32_t isrs_autotune(isrs_ctx* ctx, isrs_batch* batch, const isrs_numerics* numerics, const char* cache_path);
 
 /* Launch shape in use on a batch: mode 0 = one block per unit, 1 = queue;
- * blocks_per_cu, sort (1 = cost-sorted) and strips per unit. */
+ * blocks_per_cu, sort (1 = cost-sorted) and slices (of 256 point runs) per unit. */
 int32_t isrs_batch_get_tuning(const isrs_batch* batch, int32_t* mode, int32_t* blocks_per_cu, int32_t* sort,
-                              int32_t* strips);
+                              int32_t* slices);
 
 /* ------------------------------------------------------------------------
  * Learned surrogate of the per-span FWM efficiency (an MLP ensemble).

@@ -304,7 +304,7 @@ class Batch:
     def tuning(self):
         v = [C.c_int32() for _ in range(4)]
         self._e._check(self._e._L.isrs_batch_get_tuning(self._h, *[C.byref(x) for x in v]))
-        return {"mode": v[0].value, "blocks_per_cu": v[1].value, "sort": v[2].value, "strips": v[3].value}
+        return {"mode": v[0].value, "blocks_per_cu": v[1].value, "sort": v[2].value, "slices": v[3].value}
 
 
 def _fp(a):

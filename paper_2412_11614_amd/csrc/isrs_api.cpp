@@ -104,12 +104,12 @@ struct Tuning {
     int mode = 0;           // 0: one block per work unit, 1: persistent blocks on a queue
     int blocks_per_cu = 0;  // queue mode; 0 = as many as fit
     int sort = 1;           // queue mode: cost-sorted order
-    int spb = 0;            // tile strips per unit; 0 = automatic
+    int spb = 0;            // slices per unit; 0 = automatic
 };
 
 // Everything one evaluation uploads and launches.
 struct Plan {
-    int N = 0, n_f = 0, AD = 0, nt = 0, n_groups = 1, spb = 1;
+    int N = 0, n_f = 0, AD = 0, n_slices = 0, n_groups = 1, spb = 1;
     bool fp32 = false;
     int mu_method = 0;
     std::vector<LinkDesc> links;
@@ -118,6 +118,7 @@ struct Plan {
     std::vector<SegRow32> seg32;
     std::vector<double> Sg, wt, s3;
     std::vector<int> livep;
+    std::vector<int> runs;           // runs of PPT points by anti-diagonal (region kernel layout)
     std::vector<double> power, phi, psi;
     std::vector<InstDesc> insts;
     std::vector<SquareItem> items;
@@ -135,7 +136,7 @@ struct Plan {
 
 // Device side of a plan.
 struct Workspace {
-    DevBuf links, spans, seg, Sg, wt, s3, livep, insts, items, order, partD, partE, Y, dlist, counter, out,
+    DevBuf links, spans, seg, Sg, wt, s3, livep, runs, insts, items, order, partD, partE, Y, dlist, counter, out,
         power, phi, psi, sur;
     HostBuf stage;
     hipEvent_t ev_upload = nullptr;
@@ -284,7 +285,11 @@ void plan_begin(const isrs_numerics* nu, Plan& p)
     p.N = nu->n1;
     p.n_f = nu->n_f;
     p.AD = 2 * p.N - 1;
-    p.nt = (p.N + TILE - 1) / TILE;
+    // runs of PPT consecutive points along each anti-diagonal m = i + j
+    p.runs.clear();
+    for (int m = 0; m < p.AD; ++m)
+        for (int i = std::max(0, m - p.N + 1); i <= std::min(m, p.N - 1); i += PPT) p.runs.push_back(m << RUN_SHIFT | i);
+    p.n_slices = (int)((p.runs.size() + THREADS - 1) / THREADS);
     p.fp32 = nu->precision == ISRS_PREC_FP32_PHASE64;
     p.mu_method = nu->mu_method;
 }
@@ -532,12 +537,12 @@ void plan_finish(Plan& p, size_t ycap, const Tuning& tu, int max_items = 0)
     }
     p.chunk_begin.push_back((int)p.items.size());
     p.dchunk_begin.push_back((int)p.dlist.size());
-    // strip groups: by default enough units to fill the chip with few partials
+    // slice groups: by default enough units to fill the chip with few partials
     const long long n_items = (long long)p.items.size();
-    int spb = tu.spb > 0 ? std::min(tu.spb, p.nt)
-                         : (int)std::min<long long>(p.nt, std::max<long long>(1, n_items * p.nt / 32768));
+    int spb = tu.spb > 0 ? std::min(tu.spb, p.n_slices)
+                         : (int)std::min<long long>(p.n_slices, std::max<long long>(1, n_items * p.n_slices / 32768));
     p.spb = spb;
-    p.n_groups = (p.nt + spb - 1) / spb;
+    p.n_groups = (p.n_slices + spb - 1) / spb;
     // queue order per chunk: longest units first (their cost splits evenly over groups)
     const size_t n_units = p.items.size() * p.n_groups;
     p.order.resize(n_units);
@@ -610,6 +615,14 @@ std::string plan_check(const Plan& p)
         if (it.k1 < 0 || it.k2 < 0 || it.k1 >= d.n_ch || it.k2 >= d.n_ch) return "square channel out of bounds";
     }
     if (p.order.size() != p.items.size() * (size_t)p.n_groups) return "queue order has the wrong length";
+    if (p.N > RUN_MASK + 1 || p.runs.empty() || p.n_slices != (int)((p.runs.size() + THREADS - 1) / THREADS))
+        return "run table does not match the grid";
+    for (size_t c0 = 0; c0 < p.runs.size(); c0 += THREADS) {
+        const size_t c1 = std::min(c0 + THREADS, p.runs.size()) - 1;
+        if ((p.runs[c1] >> RUN_SHIFT) - (p.runs[c0] >> RUN_SHIFT) + 1 > NAD) return "slice spans too many anti-diagonals";
+    }
+    for (int r : p.runs)
+        if ((r >> RUN_SHIFT) >= p.AD || (r & RUN_MASK) >= p.N) return "run out of the grid";
     return "";
 }
 
@@ -628,7 +641,7 @@ int32_t plan_upload(isrs_ctx* c, Workspace& w, const Plan& p, hipStream_t st)
     if (!bad.empty()) return fail(c, ISRS_E_ARG, "internal plan check: " + bad);
     if (w.ev_upload) HIP_TRY(c, hipEventSynchronize(w.ev_upload));  // previous copies out of staging
     const size_t need = staged(p.links) + staged(p.spans) + (p.fp32 ? staged(p.seg32) : staged(p.seg64)) +
-                        staged(p.Sg) + staged(p.wt) + staged(p.s3) + staged(p.livep) + staged(p.insts) +
+                        staged(p.Sg) + staged(p.wt) + staged(p.s3) + staged(p.livep) + staged(p.runs) + staged(p.insts) +
                         staged(p.items) + staged(p.dlist) + staged(p.order) + staged(p.power) + staged(p.phi) +
                         staged(p.psi);
     HIP_TRY(c, w.stage.ensure(need));
@@ -645,6 +658,7 @@ int32_t plan_upload(isrs_ctx* c, Workspace& w, const Plan& p, hipStream_t st)
     if ((rc = upload(c, st, w.wt, p.wt, stage))) return rc;
     if ((rc = upload(c, st, w.s3, p.s3, stage))) return rc;
     if ((rc = upload(c, st, w.livep, p.livep, stage))) return rc;
+    if ((rc = upload(c, st, w.runs, p.runs, stage))) return rc;
     if ((rc = upload(c, st, w.insts, p.insts, stage))) return rc;
     if ((rc = upload(c, st, w.items, p.items, stage))) return rc;
     if ((rc = upload(c, st, w.dlist, p.dlist, stage))) return rc;
@@ -699,7 +713,9 @@ int32_t plan_enqueue(isrs_ctx* c, Workspace& w, const Plan& p, const Tuning& tu,
     ra.ybuf = w.Y.p;
     ra.n_groups = p.n_groups;
     ra.spb = p.spb;
-    ra.nt = p.nt;
+    ra.n_slices = p.n_slices;
+    ra.runs = w.runs.as<int>();
+    ra.n_runs = (int)p.runs.size();
     ra.N = p.N;
     ra.mu_method = p.mu_method;
     int blocks = 0;
@@ -1093,7 +1109,7 @@ std::string tune_key(const isrs_batch* b, const isrs_numerics* nu, const char* a
         for (int s = 0; s < L.n_sp; ++s) kmax = std::max(kmax, (int)std::ceil(L.spans[s].length_km / nu->dz_km));
     }
     std::ostringstream os;
-    os << arch << "|N" << nu->n1 << "|K" << ((kmax + 31) / 32) * 32 << "|S" << ((smax + 7) / 8) * 8 << "|P"
+    os << arch << "|runs|N" << nu->n1 << "|K" << ((kmax + 31) / 32) * 32 << "|S" << ((smax + 7) / 8) * 8 << "|P"
        << nu->precision << "|M" << nu->mu_method << "|F" << nu->n_f;
     return os.str();
 }
@@ -1106,13 +1122,13 @@ std::map<std::string, std::vector<double>> read_cache(const char* path)
     std::ifstream f(path);
     std::string line;
     while (std::getline(f, line)) {
-        // {"key": "...", "mode": m, "blocks_per_cu": b, "sort": s, "strips": p, "ms": t}
+        // {"key": "...", "mode": m, "blocks_per_cu": b, "sort": s, "slices": p, "ms": t}
         auto kpos = line.find("\"key\": \"");
         if (kpos == std::string::npos) continue;
         auto kend = line.find('"', kpos + 8);
         std::string key = line.substr(kpos + 8, kend - kpos - 8);
         std::vector<double> v;
-        for (const char* name : {"\"mode\": ", "\"blocks_per_cu\": ", "\"sort\": ", "\"strips\": ", "\"ms\": "}) {
+        for (const char* name : {"\"mode\": ", "\"blocks_per_cu\": ", "\"sort\": ", "\"slices\": ", "\"ms\": "}) {
             auto p = line.find(name);
             if (p == std::string::npos) break;
             v.push_back(std::atof(line.c_str() + p + std::strlen(name)));
@@ -1132,7 +1148,7 @@ bool write_cache(const char* path, const std::map<std::string, std::vector<doubl
     for (auto& kv : m) {
         f << "{\"key\": \"" << kv.first << "\", \"mode\": " << (int)kv.second[0]
           << ", \"blocks_per_cu\": " << (int)kv.second[1] << ", \"sort\": " << (int)kv.second[2]
-          << ", \"strips\": " << (int)kv.second[3] << ", \"ms\": " << kv.second[4] << "}"
+          << ", \"slices\": " << (int)kv.second[3] << ", \"ms\": " << kv.second[4] << "}"
           << (++i < m.size() ? ",\n" : "\n");
     }
     f << "]\n";
@@ -1700,14 +1716,14 @@ int32_t isrs_batch_eval(isrs_ctx* c, isrs_batch* b, const isrs_numerics* nu, dou
     }
 }
 
-int32_t isrs_batch_get_tuning(const isrs_batch* b, int32_t* mode, int32_t* bpc, int32_t* sort, int32_t* strips)
+int32_t isrs_batch_get_tuning(const isrs_batch* b, int32_t* mode, int32_t* bpc, int32_t* sort, int32_t* slices)
 {
     try {
         if (!b) return ISRS_E_ARG;
         if (mode) *mode = b->tuning.mode;
         if (bpc) *bpc = b->tuning.blocks_per_cu;
         if (sort) *sort = b->tuning.sort;
-        if (strips) *strips = b->planned ? b->plan.spb : b->tuning.spb;
+        if (slices) *slices = b->planned ? b->plan.spb : b->tuning.spb;
         return ISRS_OK;
     } catch (...) {
         return abi_exception(nullptr);
@@ -1736,15 +1752,17 @@ int32_t isrs_autotune(isrs_ctx* c, isrs_batch* b, const isrs_numerics* nu, const
             b->drop_graph();
             return batch_plan(c, b, nu);
         }
-        // candidates: grid mode at two strip groupings, queue mode with 1..3
-        // blocks per CU, sorted and natural order
-        const int nt = (nu->n1 + TILE - 1) / TILE;
+        // candidates: grid mode at one slice or all slices of a square per
+        // unit, queue mode with 1..4 blocks per CU, sorted and natural order
+        Plan shape;
+        plan_begin(nu, shape);
+        const int ns = shape.n_slices;
         std::vector<Tuning> cands;
-        for (int spb : {1, nt}) {
+        for (int spb : {1, ns}) {
             cands.push_back({0, 0, 0, spb});
-            for (int bpc : {1, 2, 3})
+            for (int bpc : {1, 2, 3, 4})
                 for (int sort : {1, 0}) cands.push_back({1, bpc, sort, spb});
-            if (nt == 1) break;
+            if (ns == 1) break;
         }
         const bool prof = c->profiling;
         c->profiling = true;

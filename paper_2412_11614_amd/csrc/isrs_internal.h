@@ -10,12 +10,15 @@
 
 namespace isrs {
 
-// Region tile: TILE x TILE grid points per pass, 256 threads, each thread
-// owns 4 points of one tile column.
-constexpr int TILE = 32;
+// Region kernel: 256 threads; each owns a run of PPT consecutive points of
+// one anti-diagonal of the N x N grid.  Runs are listed by anti-diagonal, and
+// a slice (THREADS consecutive runs) spans at most NAD anti-diagonals for
+// every N (59 at most, at N = 30), which bounds the staged LDS rows.
 constexpr int THREADS = 256;
-constexpr int PPT = 4;                // points per thread per tile
-constexpr int NAD = 2 * TILE - 1;     // anti-diagonals crossing a tile
+constexpr int PPT = 4;                // points per run
+constexpr int NAD = 63;               // staged anti-diagonal rows per slice
+constexpr int RUN_SHIFT = 13;         // run = m << RUN_SHIFT | first column, N <= 8192
+constexpr int RUN_MASK = (1 << RUN_SHIFT) - 1;
 constexpr int STAGE_RUN = 8;          // anti-diagonals per staging run (one exp, then a recurrence)
 
 // Forms of the per-span FWM factor run by the region kernel.
@@ -95,7 +98,7 @@ struct SquareItem {
     float mult;      // 2 for k1 < k2 (mirror square folded in), else 1
 };
 
-// A launch covers work units [unit0, unit0 + n_units); unit u is strip group
+// A launch covers work units [unit0, unit0 + n_units); unit u is slice group
 // u % n_groups of square u / n_groups.  With a queue, blocks pop positions
 // from *counter and run unit order[unit0 + pos] (a cost-sorted permutation of
 // the launch's units); without one, block b runs unit unit0 + b.
@@ -115,9 +118,11 @@ struct RegionArgs {
     int* counter;             // queue mode: head counter (zeroed before the launch)
     int unit0;
     int n_units;
-    int n_groups;             // strip groups per square
-    int spb;                  // tile strips per group
-    int nt;                   // tiles per side
+    int n_groups;             // slice groups per square
+    int spb;                  // slices per group
+    int n_slices;             // slices per square
+    const int* runs;          // [n_runs] runs of the N x N grid by anti-diagonal
+    int n_runs;
     int N;
     int mu_method;            // MU_SEG, MU_MAC, MU_INT or MU_SUR
     const float* sur_tab;     // MU_SUR: ln(|mu|^2 / |eta_6|^2) per (point, span), NaN = closed form;

@@ -17,10 +17,10 @@
 //   b_k = g_k + t b_{k+1} - s b_{k+2},   P(q) = b_0 - conj(q) b_1,
 // two real FMAs per segment (q and conj(q) are the roots of x^2 - t x + s).
 // s = exp(-2 alpha Delta) is a per-span constant.  g_k depends on the point
-// only through f1 + f2 (its anti-diagonal), so a tile stages g for its 63
-// anti-diagonals in LDS; each wave covers 8 x 8 point blocks, so the 64 lanes
-// of a read touch 15 rows and share them.  Phases are formed in FP64 in
-// revolutions and reduced to [-1/2, 1/2] before the sine / cosine.
+// only through f1 + f2 (its anti-diagonal), so each thread owns PPT
+// consecutive points of one anti-diagonal and reads one staged LDS row for
+// all of them.  Phases are formed in FP64 in revolutions and reduced to
+// [-1/2, 1/2] before the sine / cosine.
 #include "isrs_internal.h"
 
 namespace isrs {
@@ -197,7 +197,12 @@ __device__ __forceinline__ void node_weight(int n, const R (&mr)[4], const R (&m
     }
 }
 
-// One work unit: strip group u % n_groups of square u / n_groups.
+// One work unit: slice group u % n_groups of square u / n_groups.  The
+// square's points are cut into runs of PPT consecutive points along an
+// anti-diagonal (f1 + f2 constant), ordered by anti-diagonal; a slice is
+// THREADS consecutive runs, one per thread.  The points of a thread share
+// their gain row g_k(f3), so one LDS read feeds all of them, and a block
+// stages only the few rows its slice spans.
 template <typename R, int MU>
 __device__ void region_unit(const RegionArgs& a, const int u, VecOf<R>* g_vec, double* red)
 {
@@ -206,7 +211,7 @@ __device__ void region_unit(const RegionArgs& a, const int u, VecOf<R>* g_vec, d
     using Vec = typename P::Vec;
     using Seg = typename P::Seg;
     constexpr int KC = P::KC, KP = P::KP, VW = P::VW, KPV = KP / VW;
-    // g_vec: g rows of the tile's anti-diagonals, KPV vectors per row
+    // g_vec: g rows of the slice's anti-diagonals, KPV vectors per row
 
     const int tid = threadIdx.x;
     const int item = u / a.n_groups;
@@ -231,270 +236,264 @@ __device__ void region_unit(const RegionArgs& a, const int u, VecOf<R>* g_vec, d
     const SpanConst* spans = a.spans + lk.span0;
     const Seg* seg = reinterpret_cast<const Seg*>(a.seg);
     V2* ybuf = it.y_slot >= 0 ? reinterpret_cast<V2*>(a.ybuf) + (size_t)it.y_slot * N * N : nullptr;
-
-    // wave w owns tile columns 8w..8w+7; point r of a lane is in rows 8r..8r+7
-    const int lane = tid & 63, wv = tid >> 6;
-    const int li = 8 * wv + (lane & 7), lj = lane >> 3;
     double dacc[3] = {0.0, 0.0, 0.0};
 
-    const int tj_end = min(a.nt, (grp + 1) * a.spb);
-    for (int tj = grp * a.spb; tj < tj_end; ++tj) {
-        for (int ti = 0; ti < a.nt; ++ti) {
-            const int i0 = ti * TILE, j0 = tj * TILE, mb = i0 + j0;
-            // a tile is skipped when none of its anti-diagonals is live
-            bool live = false;
-            const int hi = min(mb + NAD, AD);
+    const int sl_end = min(a.n_slices, (grp + 1) * a.spb);
+    for (int sl = grp * a.spb; sl < sl_end; ++sl) {
+        const int c0 = sl * THREADS;
+        const int c1 = min(c0 + THREADS, a.n_runs) - 1;       // last run of the slice
+        const int mlo = a.runs[c0] >> RUN_SHIFT, mhi = a.runs[c1] >> RUN_SHIFT;
+        // this thread's run: anti-diagonal m, points i0 .. i0 + PPT - 1 (i <= ihi)
+        const bool has = c0 + tid <= c1;
+        const int run = a.runs[has ? c0 + tid : c1];
+        const int m = run >> RUN_SHIFT, i0 = run & RUN_MASK;
+        const int ihi = min(m, N - 1);
+        // a slice is skipped when none of its anti-diagonals is live
+        bool live = false;
 #pragma unroll
-            for (int l = 0; l < 3; ++l)
-                if ((it.lmask >> l) & 1) live |= livep[l * (AD + 1) + hi] - livep[l * (AD + 1) + mb] > 0;
-            const int ip = i0 + li;
-            if (!live) {
-                if (ybuf) {
+        for (int l = 0; l < 3; ++l)
+            if ((it.lmask >> l) & 1) live |= livep[l * (AD + 1) + mhi + 1] - livep[l * (AD + 1) + mlo] > 0;
+        if (!live) {
+            if (ybuf && has) {
 #pragma unroll
-                    for (int r = 0; r < PPT; ++r) {
-                        const int jr = j0 + lj + 8 * r;
-                        if (ip < N && jr < N) ybuf[(size_t)jr * N + ip] = V2{R(0), R(0)};
-                    }
+                for (int r = 0; r < PPT; ++r)
+                    if (i0 + r <= ihi) ybuf[(size_t)(m - i0 - r) * N + i0 + r] = V2{R(0), R(0)};
+            }
+            continue;
+        }
+
+        // per point d12 = (f1 - f)(f2 - f) in FP64; a + b and f3 are the run's
+        const double ssum = sb + (m + 1 - N) * h;
+        double pa[PPT];
+        R ur[PPT], ui[PPT];  // Upsilon of each point
+#pragma unroll
+        for (int r = 0; r < PPT; ++r) {
+            const int ip = min(i0 + r, ihi);   // points past the run's end repeat its last
+            pa[r] = (d1b + (ip + 0.5 - 0.5 * N) * h) * (d2b + (m - ip + 0.5 - 0.5 * N) * h);
+            ur[r] = R(0);
+            ui[r] = R(0);
+        }
+
+        for (int s = 0; s < lk.n_sp; ++s) {
+            const SpanConst sc = spans[s];
+            // phases in revolutions are d12 times a per-run factor (Eqs. 22, 24)
+            const double fth = fma(ssum, sc.p3r, sc.p2r);
+            const double fq = fma(ssum, sc.c3r, sc.c2r);
+            // rotation of the span's contribution: gamma Pi e^{i Theta_s} (Eq. 22)
+            R gm = R(sc.gamma);
+            if (lk.gain_mode == 1) gm *= exp_r(R(sc.pi_a - sc.pi_s * ssum + sc.pi_c * cabs));
+            R rr[PPT], ri[PPT];
+#pragma unroll
+            for (int r = 0; r < PPT; ++r) {
+                R st, ct;
+                sincos_rev(frac_rev<R>(pa[r] * fth), &st, &ct);
+                rr[r] = gm * ct;
+                ri[r] = gm * st;
+            }
+            if constexpr (MU == MU_MAC) {
+                // Maclaurin form, Eqs. 4-6
+                const double fx = fma(ssum, sc.c3x, sc.c2x), fl = fma(ssum, sc.c3L, sc.c2L);
+                const R al = R(sc.alpha);
+                const R c = R(sc.pcr) * R(ssum - cabs) / al;
+#pragma unroll
+                for (int r = 0; r < PPT; ++r) {
+                    const R ch = R(pa[r] * fx);
+                    R sl, cl;
+                    sincos_rev(frac_rev<R>(pa[r] * fl), &sl, &cl);
+                    const R inv1 = R(1) / (al * al + ch * ch);
+                    const R inv2 = R(1) / (R(4) * al * al + ch * ch);
+                    // eta = (e^{(i chi - a) L} - 1) / (i chi - a)
+                    R vr = R(sc.emL) * cl - R(1), vi = R(sc.emL) * sl;
+                    const R er = (-al * vr + ch * vi) * inv1, ei = (-ch * vr - al * vi) * inv1;
+                    // (e^{(i chi - 2a) L} - 1) / (i chi - 2a)
+                    vr = R(sc.em2L) * cl - R(1);
+                    vi = R(sc.em2L) * sl;
+                    const R fr = (R(-2) * al * vr + ch * vi) * inv2, fi = (-ch * vr - R(2) * al * vi) * inv2;
+                    const R mr = er - c * (er - fr), mi = ei - c * (ei - fi);
+                    ur[r] += rr[r] * mr - ri[r] * mi;
+                    ui[r] += rr[r] * mi + ri[r] * mr;
                 }
                 continue;
             }
 
-            const double f1 = (ip + 0.5 - 0.5 * N) * h;
-            const double d1 = d1b + f1;
-            // per point: pa = d12 = (f1 - f)(f2 - f) and pb = d12 (f1 + f2), FP64
-            double pa[PPT], pb[PPT];
-            R ur[PPT], ui[PPT];  // Upsilon of each point
+            // Surrogate table (MU_SUR): mu = eta_6 e^{r / 2} with eta_6 of Eq. 6 (its
+            // phase kept), r the ensemble's residual; NaN rows take the segment
+            // form below, which then runs for the whole block.
+            bool fb[PPT];
 #pragma unroll
-            for (int r = 0; r < PPT; ++r) {
-                const int jr = j0 + lj + 8 * r;
-                const double f2 = (jr + 0.5 - 0.5 * N) * h;
-                pa[r] = d1 * (d2b + f2);
-                pb[r] = pa[r] * (sb + f1 + f2);
-                ur[r] = R(0);
-                ui[r] = R(0);
+            for (int r = 0; r < PPT; ++r) fb[r] = MU != MU_SUR;
+            if constexpr (MU == MU_SUR) {
+                const double fl = fma(ssum, sc.c3L, sc.c2L);
+                bool any = false;
+#pragma unroll
+                for (int r = 0; r < PPT; ++r) {
+                    const int ip = min(i0 + r, ihi);
+                    float rv = 0.0f;
+                    if (has)
+                        rv = a.sur_tab[(((size_t)(item - a.sur_item0) * N + (m - ip)) * N + ip) * lk.n_sp + s];
+                    fb[r] = rv != rv;
+                    any |= fb[r];
+                    if (fb[r]) continue;
+                    const R al = R(sc.alpha), ch = R(pa[r] * fq) * R(sc.wd);
+                    R sl, cl;
+                    sincos_rev(frac_rev<R>(pa[r] * fl), &sl, &cl);
+                    const R vr = R(sc.emL) * cl - R(1), vi = R(sc.emL) * sl;
+                    const R inv = recip(al * al + ch * ch);
+                    const R g = exp_r(R(0.5) * R(rv));
+                    const R mr = (-al * vr + ch * vi) * inv * g, mi = (-ch * vr - al * vi) * inv * g;
+                    ur[r] += rr[r] * mr - ri[r] * mi;
+                    ui[r] += rr[r] * mi + ri[r] * mr;
+                }
+                if (!__syncthreads_or(any)) continue;
             }
 
-            for (int s = 0; s < lk.n_sp; ++s) {
-                const SpanConst sc = spans[s];
-                // rotation of the span's contribution: gamma Pi e^{i Theta_s} (Eq. 22)
-                R rr[PPT], ri[PPT];
+            // q = e^{(i chi - alpha) Delta}.  Segment form: the span's factor
+            // c = rotation * I_0 with I_0 = (q - 1) / (i chi - alpha) multiplies
+            // P(q) = sum_k g_k q^k.  Integral form: node n of every segment gives
+            // P_n(q) = sum_k g(z_kn) q^k, weighted by
+            // W_n = e^{a} (Delta / 2) int_{-1}^{1} l_n(u) e^{a u} du, a = (i chi - alpha) Delta / 2,
+            // l_n the Lagrange basis of the nodes (exact product integration of the
+            // interpolated gain against the exponential); c = rotation.
+            constexpr int NN = MU == MU_INT ? INT_NODES : 1;
+            R qi[PPT], cr[PPT], ci[PPT], tq2[PPT];
+            R mre[MU == MU_INT ? PPT : 1][4], mim[MU == MU_INT ? PPT : 1][4];
+#pragma unroll
+            for (int r = 0; r < PPT; ++r) {
+                const double tq = pa[r] * fq;   // chi Delta / 2 pi
+                R sq, cq;
+                sincos_rev(frac_rev<R>(tq), &sq, &cq);
+                const R al = R(sc.alpha), ch = R(tq) * R(sc.wd);
+                const R qr = R(sc.em) * cq;
+                qi[r] = R(sc.em) * sq;
+                tq2[r] = R(2) * qr;
+                if constexpr (MU == MU_INT) {
+                    cr[r] = rr[r];
+                    ci[r] = ri[r];
+                    // a = (i chi - alpha) Delta / 2 and e^{a}; moments m_j = int u^j e^{a u}
+                    R sh, chh;
+                    sincos_rev(frac_rev<R>(0.5 * tq), &sh, &chh);
+                    const R hd = R(M_PI) / R(sc.wd);                       // Delta / 2
+                    const R ar = -al * hd, ai = ch * hd;
+                    const R eh = exp_r(ar);
+                    node_moments(ar, ai, eh * chh, eh * sh, mre[r], mim[r]);
+                    // fold e^{a} Delta / 2 into the moments
+                    const R fr = hd * eh * chh, fi = hd * eh * sh;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const R tr = mre[r][j] * fr - mim[r][j] * fi;
+                        mim[r][j] = mre[r][j] * fi + mim[r][j] * fr;
+                        mre[r][j] = tr;
+                    }
+                } else {
+                    const R vr = qr - R(1), vi = qi[r];
+                    const R inv = recip(al * al + ch * ch);
+                    const R i0r = (-al * vr + ch * vi) * inv;
+                    const R i0i = (-ch * vr - al * vi) * inv;
+                    cr[r] = rr[r] * i0r - ri[r] * i0i;
+                    ci[r] = rr[r] * i0i + ri[r] * i0r;
+                }
+            }
+            // Goertzel state per point; s = |q|^2 is uniform over the span
+            const R ms = R(-(sc.em * sc.em));
+            const int Kp4 = (sc.K + 3) & ~3;
+            const int nrows = mhi - mlo + 1;
+            for (int n = 0; n < NN; ++n) {
+                const int row0 = sc.off + n * sc.K;
+                R b1[PPT], b2[PPT];
 #pragma unroll
                 for (int r = 0; r < PPT; ++r) {
-                    R st, ct;
-                    sincos_rev(frac_rev<R>(fma(pa[r], sc.p2r, pb[r] * sc.p3r)), &st, &ct);
-                    R gm = R(sc.gamma);
-                    if (lk.gain_mode == 1) {
-                        const double sab = sb + f1 + (j0 + lj + 8 * r + 0.5 - 0.5 * N) * h;
-                        gm *= exp_r(R(sc.pi_a - sc.pi_s * sab + sc.pi_c * cabs));
-                    }
-                    rr[r] = gm * ct;
-                    ri[r] = gm * st;
+                    b1[r] = R(0);
+                    b2[r] = R(0);
                 }
-                if constexpr (MU == MU_MAC) {
-                    // Maclaurin form, Eqs. 4-6
+                for (int kc1 = Kp4; kc1 > 0; kc1 -= KC) {
+                    const int kc0 = kc1 > KC ? kc1 - KC : 0;
+                    const int len = kc1 - kc0;
+                    __syncthreads();  // previous readers of the staged rows are done
+                    // stage g_k(f3) = A_k exp(-zeta_k f3abs) for the slice's anti-diagonals:
+                    // an item is VW consecutive segments of a run of SRUN anti-diagonals,
+                    // one exp per segment at the run's first anti-diagonal, then the
+                    // step ratio exp(-zeta h) down the run, one vector write per row
+                    constexpr int SRUN = STAGE_RUN;
+                    const int runs = (nrows + SRUN - 1) / SRUN;
+                    const int lenv = len / VW;
+                    for (int t = tid; t < lenv * runs; t += THREADS) {
+                        const int kv = t % lenv, rn = t / lenv;
+                        const double x = x3b + (mlo + rn * SRUN + 1 - N) * h;
+                        R g[VW], rt[VW];
 #pragma unroll
-                    for (int r = 0; r < PPT; ++r) {
-                        const R al = R(sc.alpha), ch = R(fma(pa[r], sc.c2x, pb[r] * sc.c3x));
-                        R sl, cl;
-                        sincos_rev(frac_rev<R>(fma(pa[r], sc.c2L, pb[r] * sc.c3L)), &sl, &cl);
-                        const R inv1 = R(1) / (al * al + ch * ch);
-                        const R inv2 = R(1) / (R(4) * al * al + ch * ch);
-                        // eta = (e^{(i chi - a) L} - 1) / (i chi - a)
-                        R vr = R(sc.emL) * cl - R(1), vi = R(sc.emL) * sl;
-                        const R er = (-al * vr + ch * vi) * inv1, ei = (-ch * vr - al * vi) * inv1;
-                        // (e^{(i chi - 2a) L} - 1) / (i chi - 2a)
-                        vr = R(sc.em2L) * cl - R(1);
-                        vi = R(sc.em2L) * sl;
-                        const R fr = (R(-2) * al * vr + ch * vi) * inv2, fi = (-ch * vr - R(2) * al * vi) * inv2;
-                        const R x3 = R(sb + f1 + (j0 + lj + 8 * r + 0.5 - 0.5 * N) * h - cabs);
-                        const R c = R(sc.pcr) * x3 / al;
-                        const R mr = er - c * (er - fr), mi = ei - c * (ei - fi);
-                        ur[r] += rr[r] * mr - ri[r] * mi;
-                        ui[r] += rr[r] * mi + ri[r] * mr;
-                    }
-                    continue;
-                }
-
-                // Surrogate table (MU_SUR): mu = eta_6 e^{r / 2} with eta_6 of Eq. 6 (its
-                // phase kept), r the ensemble's residual; NaN rows take the segment
-                // form below, which then runs for the whole block.
-                bool fb[PPT];
-#pragma unroll
-                for (int r = 0; r < PPT; ++r) fb[r] = MU != MU_SUR;
-                if constexpr (MU == MU_SUR) {
-                    bool any = false;
-#pragma unroll
-                    for (int r = 0; r < PPT; ++r) {
-                        const int jr = j0 + lj + 8 * r;
-                        float rv = 0.0f;
-                        if (ip < N && jr < N)
-                            rv = a.sur_tab[(((size_t)(item - a.sur_item0) * N + jr) * N + ip) * lk.n_sp + s];
-                        fb[r] = rv != rv;
-                        any |= fb[r];
-                        if (fb[r]) continue;
-                        const double tq = fma(pa[r], sc.c2r, pb[r] * sc.c3r);   // chi Delta / 2 pi
-                        const R al = R(sc.alpha), ch = R(tq) * R(sc.wd);
-                        R sl, cl;
-                        sincos_rev(frac_rev<R>(fma(pa[r], sc.c2L, pb[r] * sc.c3L)), &sl, &cl);
-                        const R vr = R(sc.emL) * cl - R(1), vi = R(sc.emL) * sl;
-                        const R inv = recip(al * al + ch * ch);
-                        const R g = exp_r(R(0.5) * R(rv));
-                        const R mr = (-al * vr + ch * vi) * inv * g, mi = (-ch * vr - al * vi) * inv * g;
-                        ur[r] += rr[r] * mr - ri[r] * mi;
-                        ui[r] += rr[r] * mi + ri[r] * mr;
-                    }
-                    if (!__syncthreads_or(any)) continue;
-                }
-
-                // q = e^{(i chi - alpha) Delta}.  Segment form: the span's factor
-                // c = rotation * I_0 with I_0 = (q - 1) / (i chi - alpha) multiplies
-                // P(q) = sum_k g_k q^k.  Integral form: node n of every segment gives
-                // P_n(q) = sum_k g(z_kn) q^k, weighted by
-                // W_n = e^{a} (Delta / 2) int_{-1}^{1} l_n(u) e^{a u} du, a = (i chi - alpha) Delta / 2,
-                // l_n the Lagrange basis of the nodes (exact product integration of the
-                // interpolated gain against the exponential); c = rotation.
-                constexpr int NN = MU == MU_INT ? INT_NODES : 1;
-                R qr[PPT], qi[PPT], cr[PPT], ci[PPT], tq2[PPT];
-                R mre[MU == MU_INT ? PPT : 1][4], mim[MU == MU_INT ? PPT : 1][4];
-#pragma unroll
-                for (int r = 0; r < PPT; ++r) {
-                    const double tq = fma(pa[r], sc.c2r, pb[r] * sc.c3r);   // chi Delta / 2 pi
-                    R sq, cq;
-                    sincos_rev(frac_rev<R>(tq), &sq, &cq);
-                    const R al = R(sc.alpha), ch = R(tq) * R(sc.wd);
-                    qr[r] = R(sc.em) * cq;
-                    qi[r] = R(sc.em) * sq;
-                    tq2[r] = R(2) * qr[r];
-                    if constexpr (MU == MU_INT) {
-                        cr[r] = rr[r];
-                        ci[r] = ri[r];
-                        // a = (i chi - alpha) Delta / 2 and e^{a}; moments m_j = int u^j e^{a u}
-                        R sh, chh;
-                        sincos_rev(frac_rev<R>(0.5 * tq), &sh, &chh);
-                        const R hd = R(M_PI) / R(sc.wd);                       // Delta / 2
-                        const R ar = -al * hd, ai = ch * hd;
-                        const R eh = exp_r(ar);
-                        node_moments(ar, ai, eh * chh, eh * sh, mre[r], mim[r]);
-                        // fold e^{a} Delta / 2 into the moments
-                        const R fr = hd * eh * chh, fi = hd * eh * sh;
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            const R tr = mre[r][j] * fr - mim[r][j] * fi;
-                            mim[r][j] = mre[r][j] * fi + mim[r][j] * fr;
-                            mre[r][j] = tr;
-                        }
-                    } else {
-                        const R vr = qr[r] - R(1), vi = qi[r];
-                        const R inv = recip(al * al + ch * ch);
-                        const R i0r = (-al * vr + ch * vi) * inv;
-                        const R i0i = (-ch * vr - al * vi) * inv;
-                        cr[r] = rr[r] * i0r - ri[r] * i0i;
-                        ci[r] = rr[r] * i0i + ri[r] * i0r;
-                    }
-                }
-                // Goertzel state per point; s = |q|^2 is uniform over the span
-                const R ms = R(-(sc.em * sc.em));
-                const int Kp4 = (sc.K + 3) & ~3;
-                for (int n = 0; n < NN; ++n) {
-                    const int row0 = sc.off + n * sc.K;
-                    R b1[PPT], b2[PPT];
-#pragma unroll
-                    for (int r = 0; r < PPT; ++r) {
-                        b1[r] = R(0);
-                        b2[r] = R(0);
-                    }
-                    for (int kc1 = Kp4; kc1 > 0; kc1 -= KC) {
-                        const int kc0 = kc1 > KC ? kc1 - KC : 0;
-                        const int len = kc1 - kc0;
-                        __syncthreads();  // previous readers of the staged rows are done
-                        // stage g_k(f3) = A_k exp(-zeta_k f3abs) for the tile's anti-diagonals:
-                        // an item is VW consecutive segments of a run of SRUN anti-diagonals,
-                        // one exp per segment at the run's first anti-diagonal, then the
-                        // step ratio exp(-zeta h) down the run, one vector write per row
-                        constexpr int SRUN = STAGE_RUN;
-                        constexpr int RUNS = (NAD + SRUN - 1) / SRUN;
-                        const int lenv = len / VW;
-                        for (int t = tid; t < lenv * RUNS; t += THREADS) {
-                            const int kv = t % lenv, run = t / lenv;
-                            const double x = x3b + (mb + run * SRUN + 1 - N) * h;
-                            R g[VW], rt[VW];
-#pragma unroll
-                            for (int e = 0; e < VW; ++e) {
-                                const int k = kc0 + kv * VW + e;
-                                g[e] = R(0);
-                                rt[e] = R(0);
-                                if (k < sc.K) {
-                                    const Seg row = seg[row0 + k];
-                                    g[e] = row.A * exp_neg(row.zeta, x);
-                                    rt[e] = row.ratio;
-                                }
-                            }
-                            Vec* dst = g_vec + (run * SRUN) * KPV + kv;
-#pragma unroll
-                            for (int q = 0; q < SRUN; ++q) {
-                                if (run * SRUN + q < NAD) dst[q * KPV] = pack_vec(g);
-#pragma unroll
-                                for (int e = 0; e < VW; ++e) g[e] *= rt[e];
+                        for (int e = 0; e < VW; ++e) {
+                            const int k = kc0 + kv * VW + e;
+                            g[e] = R(0);
+                            rt[e] = R(0);
+                            if (k < sc.K) {
+                                const Seg row = seg[row0 + k];
+                                g[e] = row.A * exp_neg(row.zeta, x);
+                                rt[e] = row.ratio;
                             }
                         }
-                        __syncthreads();
-                        // every point reads its own anti-diagonal row: one base index
-                        // plus compile-time row offsets (8 rows apart per point).  Four
-                        // segments per step: b2 takes b_k, then b1 takes b_{k-1}, so the
-                        // state never moves between registers; the older state enters the
-                        // inner product, so one FMA per segment is on the dependency chain.
-                        const Vec* gb = g_vec + (li + lj) * KPV;
+                        Vec* dst = g_vec + (rn * SRUN) * KPV + kv;
+#pragma unroll
+                        for (int q = 0; q < SRUN; ++q) {
+                            if (rn * SRUN + q < nrows) dst[q * KPV] = pack_vec(g);
+#pragma unroll
+                            for (int e = 0; e < VW; ++e) g[e] *= rt[e];
+                        }
+                    }
+                    __syncthreads();
+                    // all points of the thread read one row.  Four segments per step:
+                    // b2 takes b_k, then b1 takes b_{k-1}, so the state never moves
+                    // between registers; the older state enters the inner product, so
+                    // one FMA per segment is on the dependency chain.
+                    const Vec* gb = g_vec + (m - mlo) * KPV;
 #pragma unroll 4
-                        for (int kq = len / 4 - 1; kq >= 0; --kq) {
-                            R g0[PPT], g1[PPT], g2[PPT], g3[PPT];
+                    for (int kq = len / 4 - 1; kq >= 0; --kq) {
+                        R g0, g1, g2, g3;
+                        load4(gb, kq, g0, g1, g2, g3);
 #pragma unroll
-                            for (int r = 0; r < PPT; ++r) load4(gb + r * 8 * KPV, kq, g0[r], g1[r], g2[r], g3[r]);
-#pragma unroll
-                            for (int r = 0; r < PPT; ++r) {
-                                b2[r] = fma(tq2[r], b1[r], fma(ms, b2[r], g3[r]));
-                                b1[r] = fma(tq2[r], b2[r], fma(ms, b1[r], g2[r]));
-                                b2[r] = fma(tq2[r], b1[r], fma(ms, b2[r], g1[r]));
-                                b1[r] = fma(tq2[r], b2[r], fma(ms, b1[r], g0[r]));
-                            }
+                        for (int r = 0; r < PPT; ++r) {
+                            b2[r] = fma(tq2[r], b1[r], fma(ms, b2[r], g3));
+                            b1[r] = fma(tq2[r], b2[r], fma(ms, b1[r], g2));
+                            b2[r] = fma(tq2[r], b1[r], fma(ms, b2[r], g1));
+                            b1[r] = fma(tq2[r], b2[r], fma(ms, b1[r], g0));
                         }
-                    }
-#pragma unroll
-                    for (int r = 0; r < PPT; ++r) {
-                        // P(q) = b_0 - conj(q) b_1;  Upsilon += c W_n P
-                        if (!fb[r]) continue;
-                        R pr = b1[r] - qr[r] * b2[r], pi = qi[r] * b2[r];
-                        if constexpr (MU == MU_INT) {
-                            R wr, wi;
-                            node_weight(n, mre[r], mim[r], wr, wi);
-                            const R tr = wr * pr - wi * pi;
-                            pi = wr * pi + wi * pr;
-                            pr = tr;
-                        }
-                        ur[r] += cr[r] * pr - ci[r] * pi;
-                        ui[r] += cr[r] * pi + ci[r] * pr;
                     }
                 }
-            }
-
-            // GN island sums (Eq. 17) and the coherent-sum buffer
-            const double S1 = ip < N ? Sg[ip] : 0.0;
 #pragma unroll
-            for (int r = 0; r < PPT; ++r) {
-                const int jr = j0 + lj + 8 * r;
-                if (ip >= N || jr >= N) continue;
-                const int m = mb + li + lj + 8 * r;
-                const double S2 = Sg[jr];
-                const double u2 = (double)ur[r] * (double)ur[r] + (double)ui[r] * (double)ui[r];
-                const double v = S1 * S1 * S2 * S2 * u2;
-#pragma unroll
-                for (int l = 0; l < 3; ++l)
-                    if ((it.lmask >> l) & 1) {
-                        const double w3 = s3[l * AD + m];
-                        dacc[l] += wt[l * AD + m] * w3 * w3 * v;
+                for (int r = 0; r < PPT; ++r) {
+                    // P(q) = b_0 - conj(q) b_1;  Upsilon += c W_n P
+                    if (!fb[r]) continue;
+                    R pr = b1[r] - R(0.5) * tq2[r] * b2[r], pi = qi[r] * b2[r];
+                    if constexpr (MU == MU_INT) {
+                        R wr, wi;
+                        node_weight(n, mre[r], mim[r], wr, wi);
+                        const R tr = wr * pr - wi * pi;
+                        pi = wr * pi + wi * pr;
+                        pr = tr;
                     }
-                if (ybuf) ybuf[(size_t)jr * N + ip] = V2{ur[r], ui[r]};
+                    ur[r] += cr[r] * pr - ci[r] * pi;
+                    ui[r] += cr[r] * pi + ci[r] * pr;
+                }
             }
         }
+
+        // GN island sums (Eq. 17) and the coherent-sum buffer
+        if (!has) continue;
+        double vs = 0.0;
+#pragma unroll
+        for (int r = 0; r < PPT; ++r) {
+            const int ip = i0 + r;
+            if (ip > ihi) continue;
+            const double S1 = Sg[ip], S2 = Sg[m - ip];
+            const double u2 = (double)ur[r] * (double)ur[r] + (double)ui[r] * (double)ui[r];
+            vs += S1 * S1 * S2 * S2 * u2;
+            if (ybuf) ybuf[(size_t)(m - ip) * N + ip] = V2{ur[r], ui[r]};
+        }
+#pragma unroll
+        for (int l = 0; l < 3; ++l)
+            if ((it.lmask >> l) & 1) {
+                const double w3 = s3[l * AD + m];
+                dacc[l] += wt[l * AD + m] * w3 * w3 * vs;
+            }
     }
     double* out = a.partD + (size_t)u * 3;
 #pragma unroll
@@ -504,10 +503,10 @@ __device__ void region_unit(const RegionArgs& a, const int u, VecOf<R>* g_vec, d
     }
 }
 
-// FP32: at most 168 VGPRs, three waves per SIMD; the surrogate-table variant
+// FP32: at most 128 VGPRs, four waves per SIMD; the surrogate-table variant
 // keeps both code paths live and takes two.
 template <typename R, int MU>
-constexpr int region_min_waves() { return sizeof(R) == 4 && (MU == MU_SEG || MU == MU_MAC) ? 3 : 2; }
+constexpr int region_min_waves() { return sizeof(R) == 4 && (MU == MU_SEG || MU == MU_MAC) ? 4 : 2; }
 
 template <typename R, int MU>
 __global__ void __launch_bounds__(THREADS, (region_min_waves<R, MU>())) region_kernel(RegionArgs a)

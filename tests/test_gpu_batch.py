@@ -115,7 +115,7 @@ def test_autotune_picks_a_shape_and_caches_it(engine, tmp_path):
     engine.set_profiling(False)
     cache = str(tmp_path / "tune.json")
     t = b.autotune(nu, cache, precision=FP32)
-    assert t["mode"] in (0, 1) and t["strips"] >= 1
+    assert t["mode"] in (0, 1) and t["slices"] >= 1
     entries = json.load(open(cache))
     assert len(entries) == 1 and entries[0]["ms"] > 0
     got = b.eval(nu, precision=FP32)
