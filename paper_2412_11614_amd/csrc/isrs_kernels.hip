@@ -203,8 +203,13 @@ __device__ __forceinline__ void node_weight(int n, const R (&mr)[4], const R (&m
 // THREADS consecutive runs, one per thread.  The points of a thread share
 // their gain row g_k(f3), so one LDS read feeds all of them, and a block
 // stages only the few rows its slice spans.
+// The span, run and live tables are read through restrict-qualified kernel
+// parameters: nothing the kernel writes aliases them, so their block-uniform
+// reads go through scalar loads.
 template <typename R, int MU>
-__device__ void region_unit(const RegionArgs& a, const int u, VecOf<R>* g_vec, double* red)
+__device__ void region_unit(const RegionArgs& a, const int u, VecOf<R>* g_vec, double* red,
+                            const SpanConst* __restrict__ spans_all, const int* __restrict__ runs,
+                            const int* __restrict__ livep_all)
 {
     using P = Prec<R>;
     using V2 = typename P::V2;
@@ -231,9 +236,9 @@ __device__ void region_unit(const RegionArgs& a, const int u, VecOf<R>* g_vec, d
     const double cabs = (in.cut - half_grid) * df + in.f;
     const double* wt = a.wt + lk.tab0 + (size_t)in.nf_idx * 3 * AD;
     const double* s3 = a.s3 + lk.tab0 + (size_t)in.nf_idx * 3 * AD;
-    const int* livep = a.livep + lk.livep0 + (size_t)in.nf_idx * 3 * (AD + 1);
+    const int* livep = livep_all + lk.livep0 + (size_t)in.nf_idx * 3 * (AD + 1);
     const double* Sg = a.Sg + lk.sg0;
-    const SpanConst* spans = a.spans + lk.span0;
+    const SpanConst* spans = spans_all + lk.span0;
     const Seg* seg = reinterpret_cast<const Seg*>(a.seg);
     V2* ybuf = it.y_slot >= 0 ? reinterpret_cast<V2*>(a.ybuf) + (size_t)it.y_slot * N * N : nullptr;
     double dacc[3] = {0.0, 0.0, 0.0};
@@ -242,10 +247,10 @@ __device__ void region_unit(const RegionArgs& a, const int u, VecOf<R>* g_vec, d
     for (int sl = grp * a.spb; sl < sl_end; ++sl) {
         const int c0 = sl * THREADS;
         const int c1 = min(c0 + THREADS, a.n_runs) - 1;       // last run of the slice
-        const int mlo = a.runs[c0] >> RUN_SHIFT, mhi = a.runs[c1] >> RUN_SHIFT;
+        const int mlo = runs[c0] >> RUN_SHIFT, mhi = runs[c1] >> RUN_SHIFT;
         // this thread's run: anti-diagonal m, points i0 .. i0 + PPT - 1 (i <= ihi)
         const bool has = c0 + tid <= c1;
-        const int run = a.runs[has ? c0 + tid : c1];
+        const int run = runs[has ? c0 + tid : c1];
         const int m = run >> RUN_SHIFT, i0 = run & RUN_MASK;
         const int ihi = min(m, N - 1);
         // a slice is skipped when none of its anti-diagonals is live
@@ -509,17 +514,21 @@ template <typename R, int MU>
 constexpr int region_min_waves() { return sizeof(R) == 4 && (MU == MU_SEG || MU == MU_MAC) ? 4 : 2; }
 
 template <typename R, int MU>
-__global__ void __launch_bounds__(THREADS, (region_min_waves<R, MU>())) region_kernel(RegionArgs a)
+__global__ void __launch_bounds__(THREADS, (region_min_waves<R, MU>())) region_kernel(RegionArgs a, const SpanConst* __restrict__ spans,
+                                                                                   const int* __restrict__ runs,
+                                                                                   const int* __restrict__ livep)
 {
     __shared__ VecOf<R> g_vec[NAD * (Prec<R>::KP / Prec<R>::VW)];
     __shared__ double red[THREADS / 64];
-    region_unit<R, MU>(a, a.unit0 + blockIdx.x, g_vec, red);
+    region_unit<R, MU>(a, a.unit0 + blockIdx.x, g_vec, red, spans, runs, livep);
 }
 
 // Persistent blocks on a queue: every block pops unit positions until the
 // launch's units are exhausted, so every block reaches the exit.
 template <typename R, int MU>
-__global__ void __launch_bounds__(THREADS, (region_min_waves<R, MU>())) region_queue_kernel(RegionArgs a)
+__global__ void __launch_bounds__(THREADS, (region_min_waves<R, MU>())) region_queue_kernel(RegionArgs a, const SpanConst* __restrict__ spans,
+                                                                                         const int* __restrict__ runs,
+                                                                                         const int* __restrict__ livep)
 {
     __shared__ VecOf<R> g_vec[NAD * (Prec<R>::KP / Prec<R>::VW)];
     __shared__ double red[THREADS / 64];
@@ -532,7 +541,7 @@ __global__ void __launch_bounds__(THREADS, (region_min_waves<R, MU>())) region_q
         const int pos = pos_s;
         __syncthreads();
         if (pos < 0 || pos >= a.n_units) break;
-        region_unit<R, MU>(a, a.order[a.unit0 + pos], g_vec, red);
+        region_unit<R, MU>(a, a.order[a.unit0 + pos], g_vec, red, spans, runs, livep);
     }
 }
 
@@ -752,9 +761,9 @@ template <typename R, int MU>
 hipError_t launch_region_t(const RegionArgs& a, int blocks, hipStream_t st)
 {
     if (blocks > 0)
-        hipLaunchKernelGGL((region_queue_kernel<R, MU>), dim3(blocks), dim3(THREADS), 0, st, a);
+        hipLaunchKernelGGL((region_queue_kernel<R, MU>), dim3(blocks), dim3(THREADS), 0, st, a, a.spans, a.runs, a.livep);
     else
-        hipLaunchKernelGGL((region_kernel<R, MU>), dim3(a.n_units), dim3(THREADS), 0, st, a);
+        hipLaunchKernelGGL((region_kernel<R, MU>), dim3(a.n_units), dim3(THREADS), 0, st, a, a.spans, a.runs, a.livep);
     return hipGetLastError();
 }
 
