@@ -343,6 +343,14 @@ void plan_link_tables(const LinkInput& L, const isrs_numerics* nu, Plan& p)
         q.em2L = std::exp(-2.0 * alpha * len);
         q.alpha = alpha;
         q.gamma = sp.gamma_w_km;
+        q.f_alpha = (float)q.alpha;
+        q.f_em = (float)q.em;
+        q.f_ms = (float)(-(q.em * q.em));
+        q.f_wd = (float)q.wd;
+        q.f_gamma = (float)q.gamma;
+        q.f_emL = (float)q.emL;
+        q.f_em2L = (float)q.em2L;
+        q.f_pad = 0.0f;
         q.pcr = ptot * sp.cr_w_km_thz;
         q.K = K;
         q.off = (int)p.seg64.size();

@@ -52,6 +52,8 @@ struct SpanConst {
     double pi_a, pi_s, pi_c;  // LOSS_ONLY gain: ln Pi_s = pi_a - pi_s (a+b) + pi_c c
     int K;                 // segments
     int off;               // offset of the span's rows in the segment tables
+    // FP32 copies for the FP32 integrand (no per-wave conversions)
+    float f_alpha, f_em, f_ms, f_wd, f_gamma, f_emL, f_em2L, f_pad;  // f_ms = -em^2
 };
 
 // Segment table row k of a span: SRS gain at z_k = A exp(-zeta f3abs)

@@ -63,6 +63,18 @@ __device__ __forceinline__ void sincos_rev(double t, double* s, double* c)
 __device__ __forceinline__ float exp_r(float x) { return expf(x); }
 __device__ __forceinline__ double exp_r(double x) { return exp(x); }
 
+// a span constant in the working precision (FP32 copies are made on the host)
+template <typename R>
+__device__ __forceinline__ R spc_r(double d, float f)
+{
+    if constexpr (sizeof(R) == 4) return f;
+    else return d;
+}
+
+// e^x of a modest argument: FP32 through the hardware base-2 exponential
+__device__ __forceinline__ float exp_fast(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
+__device__ __forceinline__ double exp_fast(double x) { return exp(x); }
+
 // exp(-zeta x): FP32 through the hardware base-2 exponential, FP64 exact
 __device__ __forceinline__ float exp_neg(float zeta, double x)
 {
@@ -285,8 +297,8 @@ __device__ void region_unit(const RegionArgs& a, const int u, VecOf<R>* g_vec, d
             const double fth = fma(ssum, sc.p3r, sc.p2r);
             const double fq = fma(ssum, sc.c3r, sc.c2r);
             // rotation of the span's contribution: gamma Pi e^{i Theta_s} (Eq. 22)
-            R gm = R(sc.gamma);
-            if (lk.gain_mode == 1) gm *= exp_r(R(sc.pi_a - sc.pi_s * ssum + sc.pi_c * cabs));
+            R gm = spc_r<R>(sc.gamma, sc.f_gamma);
+            if (lk.gain_mode == 1) gm *= exp_fast(R(sc.pi_a - sc.pi_s * ssum + sc.pi_c * cabs));
             R rr[PPT], ri[PPT];
 #pragma unroll
             for (int r = 0; r < PPT; ++r) {
@@ -298,7 +310,7 @@ __device__ void region_unit(const RegionArgs& a, const int u, VecOf<R>* g_vec, d
             if constexpr (MU == MU_MAC) {
                 // Maclaurin form, Eqs. 4-6
                 const double fx = fma(ssum, sc.c3x, sc.c2x), fl = fma(ssum, sc.c3L, sc.c2L);
-                const R al = R(sc.alpha);
+                const R al = spc_r<R>(sc.alpha, sc.f_alpha);
                 const R c = R(sc.pcr) * R(ssum - cabs) / al;
 #pragma unroll
                 for (int r = 0; r < PPT; ++r) {
@@ -308,11 +320,12 @@ __device__ void region_unit(const RegionArgs& a, const int u, VecOf<R>* g_vec, d
                     const R inv1 = R(1) / (al * al + ch * ch);
                     const R inv2 = R(1) / (R(4) * al * al + ch * ch);
                     // eta = (e^{(i chi - a) L} - 1) / (i chi - a)
-                    R vr = R(sc.emL) * cl - R(1), vi = R(sc.emL) * sl;
+                    const R emL = spc_r<R>(sc.emL, sc.f_emL), em2L = spc_r<R>(sc.em2L, sc.f_em2L);
+                    R vr = emL * cl - R(1), vi = emL * sl;
                     const R er = (-al * vr + ch * vi) * inv1, ei = (-ch * vr - al * vi) * inv1;
                     // (e^{(i chi - 2a) L} - 1) / (i chi - 2a)
-                    vr = R(sc.em2L) * cl - R(1);
-                    vi = R(sc.em2L) * sl;
+                    vr = em2L * cl - R(1);
+                    vi = em2L * sl;
                     const R fr = (R(-2) * al * vr + ch * vi) * inv2, fi = (-ch * vr - R(2) * al * vi) * inv2;
                     const R mr = er - c * (er - fr), mi = ei - c * (ei - fi);
                     ur[r] += rr[r] * mr - ri[r] * mi;
@@ -339,10 +352,11 @@ __device__ void region_unit(const RegionArgs& a, const int u, VecOf<R>* g_vec, d
                     fb[r] = rv != rv;
                     any |= fb[r];
                     if (fb[r]) continue;
-                    const R al = R(sc.alpha), ch = R(pa[r] * fq) * R(sc.wd);
+                    const R al = spc_r<R>(sc.alpha, sc.f_alpha), ch = R(pa[r] * fq) * spc_r<R>(sc.wd, sc.f_wd);
                     R sl, cl;
                     sincos_rev(frac_rev<R>(pa[r] * fl), &sl, &cl);
-                    const R vr = R(sc.emL) * cl - R(1), vi = R(sc.emL) * sl;
+                    const R emL = spc_r<R>(sc.emL, sc.f_emL);
+                    const R vr = emL * cl - R(1), vi = emL * sl;
                     const R inv = recip(al * al + ch * ch);
                     const R g = exp_r(R(0.5) * R(rv));
                     const R mr = (-al * vr + ch * vi) * inv * g, mi = (-ch * vr - al * vi) * inv * g;
@@ -367,9 +381,10 @@ __device__ void region_unit(const RegionArgs& a, const int u, VecOf<R>* g_vec, d
                 const double tq = pa[r] * fq;   // chi Delta / 2 pi
                 R sq, cq;
                 sincos_rev(frac_rev<R>(tq), &sq, &cq);
-                const R al = R(sc.alpha), ch = R(tq) * R(sc.wd);
-                const R qr = R(sc.em) * cq;
-                qi[r] = R(sc.em) * sq;
+                const R al = spc_r<R>(sc.alpha, sc.f_alpha), ch = R(tq) * spc_r<R>(sc.wd, sc.f_wd);
+                const R em = spc_r<R>(sc.em, sc.f_em);
+                const R qr = em * cq;
+                qi[r] = em * sq;
                 tq2[r] = R(2) * qr;
                 if constexpr (MU == MU_INT) {
                     cr[r] = rr[r];
@@ -399,7 +414,7 @@ __device__ void region_unit(const RegionArgs& a, const int u, VecOf<R>* g_vec, d
                 }
             }
             // Goertzel state per point; s = |q|^2 is uniform over the span
-            const R ms = R(-(sc.em * sc.em));
+            const R ms = spc_r<R>(-(sc.em * sc.em), sc.f_ms);
             const int Kp4 = (sc.K + 3) & ~3;
             const int nrows = mhi - mlo + 1;
             for (int n = 0; n < NN; ++n) {

@@ -55,10 +55,13 @@ def test_single_span_11ch_fp64(engine):
     assert np.max(np.abs(db(got["eta"], seg["eta"]))) <= 1e-9
 
 
-@pytest.mark.parametrize("n_grid", [40, 33, 8])
+@pytest.mark.parametrize("n_grid", [40, 33, 8, 1, 2, 3, 5, 30, 100])
 def test_mixed_egn_fp64_matches_segment_oracle(engine, n_grid):
-    """Mixed formats, uneven spans, an inactive slot, EGN terms; grids with a
-    ragged last tile (40, 33) and a single partial tile (8)."""
+    """Mixed formats, uneven spans, an inactive slot, EGN terms.  The region
+    kernel cuts each square into four-point runs along anti-diagonals and
+    slices of 256 runs: grids whose runs are all shorter than four points (1,
+    2, 3), ragged runs (5, 33), one slice spanning 59 anti-diagonals (30, the
+    largest over all grids), several slices per square (40, 100)."""
     wl = W.small_mixed(n_ch=7, n_spans=3, n_grid=n_grid)
     got = _run(engine, wl, precision=FP64)
     seg = oracle.eval_cuts(wl, method="segment")
