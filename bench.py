@@ -170,6 +170,39 @@ def integral_form_leg(eng, wl, W, torch, n_cuts=10):
     return res
 
 
+def mu_accuracy_map_leg(eng, W, torch, crs=(0.0, 0.14, 0.28, 0.56, 0.84, 1.12)):
+    """Accuracy of the two closed forms against the integral form (Eq. 23) as
+    the ISRS power transfer grows: the paper's Table I link (101 x 10 GBd,
+    19 dBm, one 100 km span), every third channel under test, Cr swept; all
+    three forms on the GPU in FP64 (the integral form is pinned to the oracle
+    by the tests)."""
+    cuts = np.arange(0, 101, 3, dtype=np.int32)
+    rows = []
+    for cr in crs:
+        wl = W.table1_1thz(cr=cr, fmt="qpsk", n_grid=10)
+        eng.load(wl)
+        eta, secs = {}, {}
+        for name, mu, kw in (("integral", 2, dict(dz=0.25)), ("segment", 0, {}), ("maclaurin", 1, {})):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            eta[name] = eng.eval_eta(wl.numerics, cuts, precision=W.PREC_FP64, mu_method=mu, **kw)["eta"]
+            secs[name] = time.perf_counter() - t0
+        sp, span = wl.spectrum, wl.link.spans[0]
+        alpha = span["alpha_db_km"] / (10.0 / np.log(10.0))
+        leff = (1.0 - np.exp(-alpha * span["length_km"])) / alpha
+        # Eq. 12: power transfer between the outermost channels
+        d_rho = 10.0 / np.log(10.0) * sp.power_w.sum() * cr * leff * sp.n_ch * sp.spacing_thz
+        row = {"cr": cr, "delta_rho_db": float(d_rho), "seconds": secs}
+        for name in ("segment", "maclaurin"):
+            e = 10 * np.log10(eta[name] / eta["integral"])
+            row[name + "_max_abs_db"] = float(np.max(np.abs(e)))
+            row[name + "_mae_db"] = float(np.mean(np.abs(e)))
+        rows.append(row)
+    return {"workload": ("Table I link, 1 x 100 km, QPSK, 10 x 10 points per square, CUTs 0, 3, ..., 99; "
+                         "closed forms at dz 1 km, integral form at 0.25 km"),
+            "rows": rows}
+
+
 def per_cut_dz_leg(eng, wl, eta_dz1, W, torch):
     """The segment form's step chosen per CUT (error model on a 32 x 32 grid,
     0.005 dB against a 0.5 km step), then the full workload with those steps."""
@@ -280,6 +313,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--grid", type=int, default=256)
     ap.add_argument("--cpu-squares", type=int, default=400)
+    ap.add_argument("--mu-map", type=int, default=1, help="closed-form accuracy map leg (0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--batch-links", type=int, default=512,
@@ -401,6 +435,9 @@ def main():
         out["integral_form"] = integral_form_leg(eng, wl, W, torch, args.integral_cuts)
     if args.per_cut_dz:
         out["per_cut_dz"] = per_cut_dz_leg(eng, wl, eta32, W, torch)
+    if args.mu_map:
+        log("closed-form accuracy map")
+        out["mu_accuracy_map"] = mu_accuracy_map_leg(eng, W, torch)
     if args.batch_links > 0:
         out["batched"] = batched_leg(eng, args.batch_links, args.plain_links, W, torch)
     if args.surrogate_points > 0:
