@@ -295,6 +295,7 @@ def surrogate_leg(eng, n_points, torch, train_rows=1 << 20, members=4):
         loop[name] = {"s": dt, "fallback_fraction": fb,
                       "eta_err_db": [float(v) for v in 10 * np.log10(eta / ref)]}
     s.close()
+    link_trained = surrogate_link_leg(eng, torch, W, train_rows, members, wl, cuts, ref)
     return {"workload": (f"{members}-member 16-256x4-1 SiLU ensemble, BF16 MFMA; trained on {train_rows} "
                          f"closed-form samples (2000 Adam steps of 1024 per member); {n_points} query points "
                          f"(100 x 100 GHz grid squares, 80-100 km spans, 17-23 dBm)"),
@@ -303,7 +304,57 @@ def surrogate_leg(eng, n_points, torch, train_rows=1 << 20, members=4):
             "fallback_fraction_bench": nfb / n_points,
             "speedup_vs_closed_form": times["closed_form"] / times["surrogate_thr_0p01_db"],
             "mlp_tflops": flop_pt * n_points / t_sur / 1e12, "mlp_peak_bf16_tflops": 2500.0,
-            "eta_in_the_loop": loop}
+            "eta_in_the_loop": loop, "link_trained": link_trained}
+
+
+def surrogate_link_leg(eng, torch, W, train_rows, members, wl, cuts, ref, n_links=64):
+    """The same ensemble trained on the query distribution of real links: points
+    drawn from the CUTs, channel pairs, grid cells and spans of n_links C+L
+    links (the benchmark link's distribution, seeds 100..), tested on points of
+    n_links held-out links (seeds 1000..) and in the loop on the benchmark link
+    (seed 2)."""
+    db = 10.0 / np.log(10.0)
+
+    def draw(seed0, n, seed):
+        b = eng.batch([W.cl_100ch_10span(seed=seed0 + i, n_grid=wl.numerics.n_grid) for i in range(n_links)])
+        x = torch.empty(n, 16, device="cuda")
+        r = torch.empty(n, device="cuda")
+        rej = eng.surrogate_datagen_batch(b, wl.numerics.n_grid, x, r, seed)
+        b.close()
+        return x, r, rej
+
+    t0 = time.perf_counter()
+    x, r, rej = draw(100, train_rows, 4)
+    t_gen = time.perf_counter() - t0
+    s = eng.surrogate(members, seed=5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.train(x, r, steps=1500, batch=1024, lr=1e-3)
+    loss = s.train(x, r, steps=500, batch=1024, lr=3e-4)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del x, r
+    xh, _, _ = draw(1000, 8192, 1000)
+    ycf = torch.empty(8192, device="cuda")
+    eng.closed_form_points(xh, ycf)
+    yh = torch.empty(8192, device="cuda")
+    held = {}
+    for thr in (float("inf"), 0.01):
+        nf = s.eval_points(xh, yh, thr)
+        err = db * (yh - ycf).double().cpu().numpy()
+        held["no_fallback" if thr == float("inf") else "thr_0p01_db"] = {
+            "rms_db": float(np.sqrt(np.mean(err ** 2))), "max_abs_db": float(np.abs(err).max()),
+            "fallback_fraction": nf / 8192}
+    eng.load(wl)
+    loop = {}
+    for name, thr in (("no_fallback", float("inf")), ("thr_0p01_db", 0.01)):
+        eta, fb = s.eval_eta(wl.numerics, cuts, thr)
+        loop[name] = {"fallback_fraction": fb, "eta_err_db": [float(v) for v in 10 * np.log10(eta / ref)]}
+    s.close()
+    return {"workload": (f"{train_rows} points from {n_links} C+L links (seeds 100-{99 + n_links}), "
+                         f"held-out points from {n_links} others (seeds 1000-{999 + n_links})"),
+            "datagen_s": t_gen, "rejected_draws": rej, "train_s": t_train,
+            "train_loss_ln2": [float(v) for v in loss], "held_out_8192": held, "eta_in_the_loop": loop}
 
 
 def main():
