@@ -165,6 +165,34 @@ def test_single_channel_and_one_segment(engine):
     assert np.max(np.abs(db(got["eta"], seg["eta"]))) <= 1e-9
 
 
+def test_largest_grid(engine):
+    """The largest grid the boundary accepts (8192 x 8192 points per square,
+    the limit of the run encoding): one channel, one segment, against the
+    oracle's segment form."""
+    sp = W.spectrum_from(1, 0.05, 0.032, 0.2, [1e-3], ["16qam"])
+    wl = W.Workload("one", sp, W.Link(W.make_spans([40.0])), W.Numerics(n_grid=8192, dz_km=100.0, egn=1),
+                    np.array([0], dtype=np.int32))
+    seg = oracle.eval_cuts(wl, method="segment")
+    for prec, bar in ((FP64, 1e-9), (FP32, 1e-3)):
+        got = _run(engine, wl, precision=prec)
+        print("N 8192 prec", prec, "dB", db(got["eta"], seg["eta"]), flush=True)
+        assert np.max(np.abs(db(got["eta"], seg["eta"]))) <= bar
+
+
+def test_no_isrs_closed_forms_are_exact(engine):
+    """Cr = 0 (no ISRS): the segment sum telescopes and the Maclaurin form
+    reduces to Eq. 6, so both equal the integral form up to rounding."""
+    wl = W.small_mixed(seed=12, n_ch=6, n_spans=3, n_grid=24)
+    spans = wl.link.spans.copy()
+    spans["cr_w_km_thz"] = 0.0
+    wl = W.Workload(wl.name, wl.spectrum, W.Link(spans), wl.numerics, wl.cuts)
+    seg = _run(engine, wl, precision=FP64)["eta"]
+    mac = _run(engine, wl, precision=FP64, mu_method=1)["eta"]
+    ref = oracle.eval_cuts(wl, method="integral")["eta"]
+    assert np.max(np.abs(db(seg, mac))) <= 1e-10
+    assert np.max(np.abs(db(seg, ref))) <= 1e-9
+
+
 def test_deterministic(engine):
     wl = W.small_mixed(n_ch=7, n_spans=3, n_grid=40)
     for prec in (FP64, FP32):
@@ -182,6 +210,9 @@ def test_errors_leave_context_usable(engine):
     assert ei.value.code == _lib.ISRS_E_ARG
     with pytest.raises(_lib.IsrsError):
         engine.eval_eta(wl.numerics, [0], n=0)
+    with pytest.raises(_lib.IsrsError) as ei:          # an empty CUT list
+        engine.eval_eta(wl.numerics, [])
+    assert ei.value.code == _lib.ISRS_E_ARG
     got = engine.eval_eta(wl.numerics, wl.cuts, precision=FP64)
     assert np.all(np.isfinite(got["eta"]))
 
