@@ -308,12 +308,17 @@ int32_t isrs_surrogate_datagen(isrs_ctx* ctx, int64_t n, uint64_t seed, float* x
                                float* y6_dev);
 
 /* As isrs_surrogate_datagen, with the query points drawn from the links of a
- * batch: a link, one of its CUTs, a pair of its active channels, a point of
- * the n_grid x n_grid square lying on a live island, and a span, each
- * uniform (SplitMix64 counters keyed by seed); f is the CUT centre.  Draws
- * outside the sampling box (or from links whose B_tot is not 10 THz) are
- * redrawn and counted in n_rejected (host, nullable).  Fails with
- * ISRS_E_ARG when 4096 draws in a row are rejected. */
+ * batch (the query distribution the surrogate meets in the loop): a link,
+ * one of its CUTs, a pair of its active channels, a midpoint of the
+ * n_grid x n_grid square lying on a live island (Eq. 16), and a span, each
+ * uniform (SplitMix64 counters keyed by seed); f is the CUT centre and Ptot
+ * the link's total launch power.  Outputs as for isrs_surrogate_datagen
+ * (device buffers owned by the caller).  Draws outside the sampling box (or
+ * from links whose B_tot is not 10 THz) are redrawn and counted in
+ * n_rejected (host, nullable).  Fails with ISRS_E_ARG when 4096 draws in a
+ * row are rejected, with nothing written.  The points are drawn on the host
+ * and copied up; the call returns after the labels are written (it
+ * synchronizes the context's stream). */
 int32_t isrs_surrogate_datagen_batch(isrs_ctx* ctx, const isrs_batch* batch, int32_t n_grid, int64_t n,
                                      uint64_t seed, float* x_dev, float* r_dev, float* y6_dev, int64_t* n_rejected);
 
