@@ -468,6 +468,13 @@ def main():
                    "horner_steps": st.horner_steps},
     }
 
+    # the host-buffer entry point (CUT list in, eta out through host memory,
+    # synchronous): the same workload with its transfers
+    t1 = time.perf_counter()
+    eng.eval_eta(wl.numerics, cuts, precision=W.PREC_FP32_PHASE64)
+    t_host = time.perf_counter() - t1
+    out["host_buffers"] = {"value": n_cut / t_host, "unit": "CUT/s", "ms_per_step": 1e3 * t_host}
+
     if not args.no_fp64:
         # accuracy gate on the full workload: FP32 path vs the FP64 path (the
         # FP64 path is parity-tested against the oracle); plus its throughput
