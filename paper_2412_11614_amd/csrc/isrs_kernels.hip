@@ -464,9 +464,11 @@ __device__ void region_unit(const RegionArgs& a, const int u, VecOf<R>* g_vec, d
                     // b2 takes b_k, then b1 takes b_{k-1}, so the state never moves
                     // between registers; the older state enters the inner product, so
                     // one FMA per segment is on the dependency chain.
+                    // threads past the slice's last run skip it: whole waves of a
+                    // square's ragged last slice then leave their SIMD to others
                     const Vec* gb = g_vec + (m - mlo) * KPV;
 #pragma unroll 4
-                    for (int kq = len / 4 - 1; kq >= 0; --kq) {
+                    for (int kq = has ? len / 4 - 1 : -1; kq >= 0; --kq) {
                         R g0, g1, g2, g3;
                         load4(gb, kq, g0, g1, g2, g3);
 #pragma unroll
