@@ -495,19 +495,34 @@ __global__ void out_backward_kernel(int rows, const float* o, const float* r, fl
     if (threadIdx.x == 0) loss_part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
-// Column sums of an fp32 [rows x cols] matrix (fixed order): out[c] = sum_r X[r, c];
-// also the output-layer gradients when H is given: out[c] = sum_r H[r, c] d[r].
-__global__ void colsum_kernel(int rows, int cols, const float* X, const __bf16* H, const float* d, float* out)
+// Column sums of an fp32 [rows x cols] matrix in a fixed order: out[c] =
+// sum_r X[r, c]; with H given, the output-layer gradient out[c] = sum_r
+// H[r, c] d[r].  A block takes CS_COLS columns; each of its CS_GROUPS row
+// groups sums a contiguous run of rows, then the group sums are added in order.
+constexpr int CS_COLS = 16, CS_GROUPS = 16;
+__global__ void __launch_bounds__(CS_COLS * CS_GROUPS) colsum_kernel(int rows, int cols, const float* X,
+                                                                      const __bf16* H, const float* d, float* out)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= cols) return;
+    __shared__ float part[CS_GROUPS][CS_COLS + 1];
+    const int cl = threadIdx.x % CS_COLS, rg = threadIdx.x / CS_COLS;
+    const int c = blockIdx.x * CS_COLS + cl;
+    const int per = (rows + CS_GROUPS - 1) / CS_GROUPS;
+    const int r0 = rg * per, r1 = min(rows, r0 + per);
     float s = 0.0f;
-    if (H) {
-        for (int r = 0; r < rows; ++r) s += (float)H[(long)r * cols + c] * d[r];
-    } else {
-        for (int r = 0; r < rows; ++r) s += X[(long)r * cols + c];
+    if (c < cols) {
+        if (H) {
+            for (int r = r0; r < r1; ++r) s += (float)H[(long)r * cols + c] * d[r];
+        } else {
+            for (int r = r0; r < r1; ++r) s += X[(long)r * cols + c];
+        }
     }
-    out[c] = s;
+    part[rg][cl] = s;
+    __syncthreads();
+    if (rg == 0 && c < cols) {
+        float t = 0.0f;
+        for (int g = 0; g < CS_GROUPS; ++g) t += part[g][cl];
+        out[c] = t;
+    }
 }
 
 // Sum of split-K partials in order.
@@ -953,9 +968,9 @@ int32_t backward(isrs_ctx* c, isrs_surrogate* s, const isrs_surrogate::Member& m
     hipLaunchKernelGGL(out_backward_kernel, dim3(blocks_for(rows, 4)), dim3(256), 0, st, rows, s->o, r,
                        (float)s->shift, (float)(1.0 / s->scale), m.p + OFF_W5, s->Z[3], s->dout, s->dZ, s->dZh, s->loss_part);
     // output layer: dw5 = H4^T dout, db5 = sum dout
-    hipLaunchKernelGGL(colsum_kernel, dim3(1), dim3(NH), 0, st, rows, NH, nullptr, s->H[3], s->dout,
-                       s->grad + OFF_W5);
-    hipLaunchKernelGGL(colsum_kernel, dim3(1), dim3(64), 0, st, rows, 1, s->dout, nullptr, nullptr,
+    hipLaunchKernelGGL(colsum_kernel, dim3(NH / CS_COLS), dim3(CS_COLS * CS_GROUPS), 0, st, rows, NH, nullptr,
+                       s->H[3], s->dout, s->grad + OFF_W5);
+    hipLaunchKernelGGL(colsum_kernel, dim3(1), dim3(CS_COLS * CS_GROUPS), 0, st, rows, 1, s->dout, nullptr, nullptr,
                        s->grad + OFF_B5);
     float* dz = s->dZ;
     __bf16* dzh = s->dZh;
@@ -976,8 +991,8 @@ int32_t backward(isrs_ctx* c, isrs_surrogate* s, const isrs_surrogate::Member& m
         hipLaunchKernelGGL(split_sum_kernel, dim3(blocks_for((int64_t)kin * NH, 256)), dim3(256), 0, st,
                            (long)kin * NH, zs, (long)kin * NH, s->part, s->grad + W_OFF[l]);
         // db_l = column sums of dZ_l
-        hipLaunchKernelGGL(colsum_kernel, dim3(1), dim3(NH), 0, st, rows, NH, dz, nullptr, nullptr,
-                           s->grad + B_OFF[l]);
+        hipLaunchKernelGGL(colsum_kernel, dim3(NH / CS_COLS), dim3(CS_COLS * CS_GROUPS), 0, st, rows, NH, dz,
+                           nullptr, nullptr, s->grad + B_OFF[l]);
         if (l == 0) break;
         // dZ_{l-1} = (dZ_l W_l^T) * silu'(Z_{l-1});  W_l rows are contiguous along the output index
         GemmArgs gd = gemm(dzh, NH, 1, m.wb[l], 1, NH, rows, NH, NH);
