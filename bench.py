@@ -106,10 +106,13 @@ def batched_leg(eng, n_links, n_plain, W, torch):
     b = eng.batch(links)
     eta_b = torch.empty(b.n_cuts, dtype=torch.float64, device="cuda")
     log(f"batched: {n_links} links, {b.n_cuts} CUTs: warm-up (plan + eager run), capture")
+    eng.set_profiling(True)                      # the eager first call also reports the work done
     t0 = time.perf_counter()
     b.eval_dev(nu, eta_b)
     torch.cuda.synchronize()
     t_first = time.perf_counter() - t0
+    st = eng.stats()
+    eng.set_profiling(False)
     b.eval_dev(nu, eta_b)                        # capture the graph
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -144,7 +147,10 @@ def batched_leg(eng, n_links, n_plain, W, torch):
             "ms_per_step": 1e3 * t_batch, "first_call_s": t_first,
             "plain_path": {"links": n_plain, "n_cut": cuts_plain, "value": cuts_plain / t_plain, "unit": "CUT/s"},
             "speedup_vs_plain": (b.n_cuts / t_batch) / (cuts_plain / t_plain),
-            "max_abs_db_batch_vs_plain": agree}
+            "max_abs_db_batch_vs_plain": agree,
+            # algorithmic FLOP of the step (8 K + 30 per live point-span) over the replay's wall time
+            "alg_tflops": st.alg_flop / t_batch / 1e12, "frac": st.alg_flop / t_batch / 1e12 / PEAK_FP32_TFLOPS,
+            "region_ms_eager": st.region_ms, "live_points": st.n_points_live}
 
 
 def integral_form_leg(eng, wl, W, torch, n_cuts=10):
