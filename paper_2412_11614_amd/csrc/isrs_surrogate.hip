@@ -623,16 +623,32 @@ __global__ void count_kernel(int64_t n, const int* flag, int* cnt)
     }
 }
 
-__global__ void scan_kernel(int nb, const int* cnt, int* off, int* total)
+// Exclusive scan of the per-block counts in one block of SCAN_T threads: each
+// thread takes a contiguous run of counts, the run totals are scanned in LDS,
+// then each thread writes its run's offsets (integer sums, so exact).
+constexpr int SCAN_T = 1024;
+__global__ void __launch_bounds__(SCAN_T) scan_kernel(int nb, const int* cnt, int* off, int* total)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        int t = 0;
-        for (int b = 0; b < nb; ++b) {
-            off[b] = t;
-            t += cnt[b];
-        }
-        *total = t;
+    __shared__ int part[SCAN_T];
+    const int t = threadIdx.x;
+    const int per = (nb + SCAN_T - 1) / SCAN_T;
+    const int b0 = min(nb, t * per), b1 = min(nb, b0 + per);
+    int sum = 0;
+    for (int b = b0; b < b1; ++b) sum += cnt[b];
+    part[t] = sum;
+    __syncthreads();
+    for (int d = 1; d < SCAN_T; d <<= 1) {     // inclusive scan of the run totals
+        const int v = t >= d ? part[t - d] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
     }
+    int base = t ? part[t - 1] : 0;
+    for (int b = b0; b < b1; ++b) {
+        off[b] = base;
+        base += cnt[b];
+    }
+    if (t == SCAN_T - 1) *total = part[SCAN_T - 1];
 }
 
 __global__ void scatter_kernel(int64_t n, const int* flag, const int* off, int64_t* idx)
@@ -1401,7 +1417,7 @@ int32_t isrs_surrogate_eval_points(isrs_ctx* c, isrs_surrogate* s, const float* 
                            nullptr, nullptr, y, thr_ln, s->flag);
         const int64_t nb = (n + CB - 1) / CB;
         hipLaunchKernelGGL(count_kernel, dim3((unsigned)nb), dim3(CB), 0, st, n, s->flag, s->cnt);
-        hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(64), 0, st, (int)nb, s->cnt, s->off, s->total);
+        hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(SCAN_T), 0, st, (int)nb, s->cnt, s->off, s->total);
         hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)nb), dim3(CB), 0, st, n, s->flag, s->off, s->idx);
         hipLaunchKernelGGL(fallback_kernel, dim3(blocks_for(n, 128)), dim3(128), 0, st, s->total, s->idx, x, y);
         S_TRY(c, hipGetLastError());
