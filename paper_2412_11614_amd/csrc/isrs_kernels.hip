@@ -525,10 +525,15 @@ __device__ void region_unit(const RegionArgs& a, const int u, VecOf<R>* g_vec, d
     }
 }
 
-// FP32: at most 128 VGPRs, four waves per SIMD; the surrogate-table variant
-// keeps both code paths live and takes two.
+// Waves per SIMD the register budget is set for: FP32 at most 128 VGPRs (four
+// waves), 168 for the FP32 integral form (three); FP64 168 for the segment
+// form (three, a few spills beat two waves), otherwise two.
 template <typename R, int MU>
-constexpr int region_min_waves() { return sizeof(R) == 4 && (MU == MU_SEG || MU == MU_MAC) ? 4 : 2; }
+constexpr int region_min_waves()
+{
+    if constexpr (sizeof(R) == 4) return MU == MU_INT ? 3 : 4;
+    else return MU == MU_SEG ? 3 : 2;
+}
 
 template <typename R, int MU>
 __global__ void __launch_bounds__(THREADS, (region_min_waves<R, MU>())) region_kernel(RegionArgs a, const SpanConst* __restrict__ spans,
