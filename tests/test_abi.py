@@ -15,8 +15,13 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "isrs_egn.h")
 
 
+def _read(path):
+    with open(path) as f:
+        return f.read()
+
+
 def _declared():
-    src = open(HEADER).read()
+    src = _read(HEADER)
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(isrs_[a-z_]+)\s*\(", src)))
 
@@ -158,5 +163,5 @@ def test_product_code_never_touches_the_oracle():
     for dirpath, _, files in os.walk(pkg):
         for f in files:
             if f.endswith((".py", ".cpp", ".hip", ".h")):
-                txt = open(os.path.join(dirpath, f)).read()
+                txt = _read(os.path.join(dirpath, f))
                 assert not pat.search(txt), f
