@@ -229,7 +229,7 @@ def per_cut_dz_leg(eng, wl, eta_dz1, W, torch):
             "max_abs_db_vs_dz1": float(np.max(np.abs(10 * np.log10(r["eta"] / eta_dz1))))}
 
 
-def surrogate_leg(eng, n_points, torch, train_rows=1 << 20, members=4):
+def surrogate_leg(eng, n_points, torch, train_rows=1 << 22, members=4):
     """Ensemble surrogate of the per-span FWM factor: training time, held-out
     error against the closed form, and throughput of inference with fallback
     (0.01 dB spread threshold) against the closed form on the same points."""
