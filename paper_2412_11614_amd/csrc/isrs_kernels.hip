@@ -467,7 +467,7 @@ __device__ void region_unit(const RegionArgs& a, const int u, VecOf<R>* g_vec, d
                     // threads past the slice's last run skip it: whole waves of a
                     // square's ragged last slice then leave their SIMD to others
                     const Vec* gb = g_vec + (m - mlo) * KPV;
-#pragma unroll 4
+#pragma unroll 8
                     for (int kq = has ? len / 4 - 1 : -1; kq >= 0; --kq) {
                         R g0, g1, g2, g3;
                         load4(gb, kq, g0, g1, g2, g3);
