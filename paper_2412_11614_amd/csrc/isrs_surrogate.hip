@@ -1206,6 +1206,7 @@ int32_t isrs_surrogate_datagen_batch(isrs_ctx* c, const isrs_batch* b, int32_t n
         if (!c) return ISRS_E_ARG;
         if (!b || n < 1 || !x || !r || n_grid < 1) return ctx_fail(c, ISRS_E_ARG, "need a batch, n >= 1, n_grid >= 1 and outputs");
         const int nl = batch_num_links(b);
+        if (nl < 1) return ctx_fail(c, ISRS_E_ARG, "the batch has no links");
         std::vector<LinkView> links(nl);
         std::vector<std::vector<int>> act(nl);
         std::vector<double> pdbm(nl);
