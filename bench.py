@@ -209,6 +209,37 @@ def mu_accuracy_map_leg(eng, W, torch, crs=(0.0, 0.14, 0.28, 0.56, 0.84, 1.12)):
             "rows": rows}
 
 
+def outer_integral_leg(eng, W, torch, n_f=5, n_cuts=10, grid=1024):
+    """The outer f-integral of Eq. 17 with n_f midpoint samples over the CUT's
+    band against the CUT-centre sample (n_f = 1), on the benchmark link at a
+    grid that resolves the FWM-efficiency ridges (1024 x 1024): time and the
+    change of eta, the NLI PSD across the middle CUT, and the convergence of
+    the CUT-centre PSD of that CUT with the (f1, f2) grid."""
+    wl = W.cl_100ch_10span(n_grid=grid)
+    cuts = np.linspace(0, len(wl.cuts) - 1, n_cuts).astype(np.int32)
+    mid = int(cuts[n_cuts // 2])
+    eng.load(wl)
+    res = {"workload": f"{n_cuts} CUTs of the benchmark link at {grid}x{grid}, n_f {n_f}"}
+    eta = {}
+    for nf in (1, n_f):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        eta[nf] = eng.eval_eta(wl.numerics, cuts, precision=W.PREC_FP32_PHASE64, n_f=nf)["eta"]
+        res[f"n_f{nf}_s"] = time.perf_counter() - t0
+    d = 10 * np.log10(eta[n_f] / eta[1])
+    res["eta_change_db"] = {"min": float(d.min()), "max": float(d.max()), "mean": float(d.mean())}
+    f, psd = eng.eval_psd(wl.numerics, [mid], precision=W.PREC_FP32_PHASE64, n_f=n_f)
+    res["psd_cut_%d" % mid] = {"f_thz": [float(v) for v in f[0]],
+                               "rel_to_centre": [float(v) for v in psd[0] / psd[0][n_f // 2]]}
+    conv = {}
+    for n in (64, 128, 256, 512, 1024):
+        w = W.cl_100ch_10span(n_grid=n)
+        eng.load(w)
+        conv[str(n)] = float(eng.eval_psd(w.numerics, [mid], precision=W.PREC_FP32_PHASE64, n_f=1)[1][0][0])
+    res["centre_psd_vs_grid_db_rel_1024"] = {k: float(10 * np.log10(v / conv["1024"])) for k, v in conv.items()}
+    return res
+
+
 def per_cut_dz_leg(eng, wl, eta_dz1, W, torch):
     """The segment form's step chosen per CUT (error model on a 32 x 32 grid,
     0.005 dB against a 0.5 km step), then the full workload with those steps."""
@@ -371,6 +402,7 @@ def main():
     ap.add_argument("--grid", type=int, default=256)
     ap.add_argument("--cpu-squares", type=int, default=400)
     ap.add_argument("--mu-map", type=int, default=1, help="closed-form accuracy map leg (0 = skip)")
+    ap.add_argument("--outer-nf", type=int, default=5, help="outer-integral leg samples (1 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--batch-links", type=int, default=512,
@@ -499,6 +531,9 @@ def main():
         out["integral_form"] = integral_form_leg(eng, wl, W, torch, args.integral_cuts)
     if args.per_cut_dz:
         out["per_cut_dz"] = per_cut_dz_leg(eng, wl, eta32, W, torch)
+    if args.outer_nf > 1:
+        log("outer-integral leg")
+        out["outer_integral"] = outer_integral_leg(eng, W, torch, n_f=args.outer_nf)
     if args.mu_map:
         log("closed-form accuracy map")
         out["mu_accuracy_map"] = mu_accuracy_map_leg(eng, W, torch)
