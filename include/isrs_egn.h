@@ -166,7 +166,7 @@ int32_t isrs_eval_eta_dev(isrs_ctx* ctx, const isrs_numerics* numerics, const in
                           double* eta_dev, double* sigma2_dev, double* terms_dev);
 
 /* eta with a sampling step per CUT: dz_km[q] replaces numerics->dz_km for
- * cuts[q] (Sec. III-D: the segment form's step can follow the COI's
+ * cuts[q] (Sec. III-C: the segment form's step can follow the COI's
  * frequency).  CUTs sharing a step share segment tables.  Outputs, units and
  * errors as isrs_eval_eta; a bad step names its CUT (ISRS_E_ARG). */
 int32_t isrs_eval_eta_dz(isrs_ctx* ctx, const isrs_numerics* numerics, const int32_t* cuts, int32_t n_cut,

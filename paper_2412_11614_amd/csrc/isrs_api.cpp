@@ -143,7 +143,7 @@ struct Workspace {
     std::vector<hipEvent_t> ev_pool;
     void release()
     {
-        DevBuf* bufs[] = {&links, &spans, &seg, &Sg, &wt, &s3, &livep, &insts, &items, &order, &partD, &partE,
+        DevBuf* bufs[] = {&links, &spans, &seg, &Sg, &wt, &s3, &livep, &runs, &insts, &items, &order, &partD, &partE,
                           &Y, &dlist, &counter, &out, &power, &phi, &psi, &sur};
         for (DevBuf* b : bufs) b->release();
         stage.release();
@@ -1588,7 +1588,7 @@ int32_t isrs_batch_create(isrs_ctx* c, const isrs_link_batch* in, isrs_batch** o
             const int c0 = in->ch_offset[l], c1 = in->ch_offset[l + 1];
             const int s0 = in->span_offset[l], s1 = in->span_offset[l + 1];
             const std::string where = "link " + std::to_string(l) + ": ";
-            if (c0 < 0 || c1 <= c0 || s0 < 0 || s1 <= s0 || (l > 0 && (c0 != in->ch_offset[l] || s0 != in->span_offset[l]))) {
+            if (c0 < 0 || c1 <= c0 || s0 < 0 || s1 <= s0 || (l == 0 && (c0 != 0 || s0 != 0))) {
                 delete b;
                 return fail(c, ISRS_E_ARG, where + "bad channel or span offsets");
             }

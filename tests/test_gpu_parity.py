@@ -217,6 +217,29 @@ def test_errors_leave_context_usable(engine):
     assert np.all(np.isfinite(got["eta"]))
 
 
+def test_non_finite_result_is_reported(engine):
+    """A Raman slope far outside any fibre's (Cr = 1e6 /W/km/THz) overflows the
+    ISRS gain of Eq. 25 (sinh and the exponential tilt), so the integrand is not
+    finite; the synchronous entry point reports ISRS_E_NUMERIC instead of
+    returning NaN, and the context stays usable."""
+    from dataclasses import replace
+
+    from paper_2412_11614_amd import _lib
+    wl = W.small_mixed(n_ch=5, n_spans=2, n_grid=8)
+    spans = wl.link.spans.copy()
+    spans["cr_w_km_thz"] = 1e6
+    bad = replace(wl, link=replace(wl.link, spans=spans))
+    engine.load(bad)
+    for prec in (FP64, FP32):
+        with pytest.raises(_lib.IsrsError) as ei:
+            engine.eval_eta(bad.numerics, bad.cuts, precision=prec)
+        assert ei.value.code == _lib.ISRS_E_NUMERIC
+    engine.load(wl)
+    got = engine.eval_eta(wl.numerics, wl.cuts, precision=FP64)["eta"]
+    ref = oracle.eval_cuts(wl, method="segment")["eta"]
+    assert np.max(np.abs(db(got, ref))) <= 1e-9
+
+
 def test_integral_form_matches_oracle_integral(engine):
     """ISRS_MU_INTEGRAL: 4-node product integration per segment reproduces the
     oracle's adaptive integral of Eq. 23; fourth-order in dz."""

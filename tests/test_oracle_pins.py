@@ -438,6 +438,141 @@ def test_grid_rule_converges_to_dense_cubature():
     assert errs[0] / errs[1] > 2.5 and errs[1] / errs[2] > 2.5, errs
 
 
+def _island_exact(spans, ptot, B, rs, k1, k2, cut, spacing, l, f=0.0):
+    """Continuous integral of |S1 S2 S3 Upsilon|^2 over island l of square (k1, k2)
+    (roll-off 0, so S = 1 / Rs inside the support): the region where
+    |f1 + f2 - f - l * spacing| <= W / 2, integrated over f1 with the exact
+    f2 limits of that strip (adaptive 2-D cubature on the split domain)."""
+    Wd = rs
+    n_ch = int(round(B / spacing))
+    nu = lambda k: (k - 0.5 * (n_ch - 1)) * spacing
+    lo, hi = l * spacing + f - Wd / 2, l * spacing + f + Wd / 2
+
+    def integrand(f2, f1):
+        u = oracle.upsilon(spans, ptot, B, nu(k1) + f1, nu(k2) + f2, nu(cut) + f, "integral")
+        return abs(u) ** 2 / rs ** 6
+
+    def f2lo(f1):
+        return max(-Wd / 2, lo - f1)
+
+    def f2hi(f1):
+        return max(f2lo(f1), min(Wd / 2, hi - f1))
+
+    v, _ = si.dblquad(integrand, -Wd / 2, Wd / 2, f2lo, f2hi, epsabs=0, epsrel=1e-10)
+    return v
+
+
+@pytest.mark.parametrize("n_ch,cut", [(1, 0), (3, 1)])
+def test_tie_rule_half_weight_converges_second_order(n_ch, cut):
+    """Roll-off 0 with Rs equal to the spacing: island boundaries f1 + f2 - f =
+    +-W/2 run through grid points of even N.  The grid rule gives such a point
+    half weight in each island it bounds (with S(f3) its inside limit, Eq. 16
+    read on the grid); each island's sum then converges at second order to the
+    continuous island integral.  A full-weight tie adds O(h) along the boundary
+    (first order, ratio 2).  One channel: the centre island only.  Three
+    channels, centre square: the side islands share the ties with it."""
+    rs = 0.032
+    sp = W.spectrum_from(n_ch, rs, rs, 0.0, np.full(n_ch, 1e-3), ["gaussian"] * n_ch)
+    spans = W.make_spans([40.0], beta2=-21.7, beta3=0.14, cr=0.028)
+    wl = W.Workload("t", sp, W.Link(spans), W.Numerics(n_grid=16, egn=0), np.array([cut]))
+    ptot, B = 1e-3 * n_ch, n_ch * rs
+    islands = [0] if n_ch == 1 else [-1, 0, 1]
+    ref = {l: _island_exact(spans, ptot, B, rs, cut, cut, cut, rs, l) for l in islands}
+    errs = {l: [] for l in islands}
+    for N in (16, 32, 64, 128):
+        t = oracle.square_terms(wl, cut, cut, cut, method="integral", n_grid=N)
+        for l in islands:
+            errs[l].append(abs(t[l + 1, 0] - ref[l]) / ref[l])
+    for l in islands:
+        e = errs[l]
+        ratios = [e[i] / e[i + 1] for i in range(len(e) - 1)]
+        print("island", l, "errors", e, "ratios", ratios)
+        assert all(3.5 < r < 4.8 for r in ratios), (l, e, ratios)
+        assert e[-1] < 1e-3
+
+
+def _srs_gain_eq14(X, x, B):
+    """SRS gain of Eq. 14 in terms of X = B Ptot Cr L_eff (1 at X = 0)."""
+    return 1.0 if X == 0 else X * math.exp(-X * x / B) / (2.0 * math.sinh(X / 2.0))
+
+
+def test_loss_only_gain_products_identical_spans_geometric_sum():
+    """LOSS_ONLY reading of Eq. 22 with Cr > 0.  With g = e^{alpha L} and
+    rho(L, x) = SRS_G(L, x) e^{-alpha L}, span s carries
+    [SRS_G(a) SRS_G(b) SRS_G(a+b-c)]^{s/2} SRS_G(c)^{(n-s)/2}; for n identical
+    spans the link function is then a geometric series,
+      Upsilon = gamma mu SRS_G(c)^{n/2} (1 - w^n) / (1 - w),
+      w = sqrt(SRS_G(a) SRS_G(b) SRS_G(a+b-c) / SRS_G(c)) e^{i chi L}."""
+    L, adb, gam, cr, ptot, B = 80.0, 0.2, 1.3, 0.03, 0.1, 10.0
+    al = adb / (10 / math.log(10))
+    X = B * ptot * cr * (1 - math.exp(-al * L)) / al
+    for n_sp in (1, 2, 5):
+        spans = W.make_spans(np.full(n_sp, L), alpha=adb, beta2=-21.7, beta3=0.14, gamma=gam, cr=cr)
+        for a, b, c in [(0.3, -1.2, 0.1), (4.0, 2.0, -3.0), (-4.5, -4.4, 4.9)]:
+            G = {x: _srs_gain_eq14(X, x, B) for x in (a, b, c, a + b - c)}
+            chi = oracle.phase_coef(-21.7, 0.14, a, b, c)
+            mu = oracle.mu(spans[0], ptot, B, a, b, c, "segment")
+            w = math.sqrt(G[a] * G[b] * G[a + b - c] / G[c]) * np.exp(1j * chi * L)
+            ref = gam * mu * G[c] ** (n_sp / 2) * (1 - w ** n_sp) / (1 - w)
+            got = oracle.upsilon(spans, ptot, B, a, b, c, "segment", gain_mode=oracle.GAIN_LOSS_ONLY)
+            # chi L reaches 1e6 rad at the band edges: phases agree to ~1e-10 rad there
+            assert abs(got - ref) <= 1e-8 * abs(ref), (n_sp, a, b, c, got, ref)
+            # the gain changes the value (Cr > 0): not the EQUALIZED result
+            eq = oracle.upsilon(spans, ptot, B, a, b, c, "segment", gain_mode=oracle.GAIN_EQUALIZED)
+            assert abs(got - eq) > 1e-3 * abs(eq)
+
+
+def test_loss_only_gain_products_two_unequal_spans():
+    """Two spans with different attenuation, Raman slope and length: the
+    LOSS_ONLY link function is the two-term expansion of Eq. 22,
+      gamma_1 mu_1 sqrt(G1(c) G2(c)) + gamma_2 mu_2 e^{i chi_1 L_1} sqrt(G1(a) G1(b) G1(x3) G2(c))."""
+    ptot, B = 0.1, 10.0
+    spans = W.make_spans([80.0, 61.0], alpha=[0.2, 0.17], beta2=[-21.7, -20.1], beta3=[0.14, 0.12],
+                         gamma=[1.3, 1.1], cr=[0.03, 0.025])
+    for a, b, c in [(0.3, -1.2, 0.1), (4.0, 2.0, -3.0)]:
+        x3 = a + b - c
+        Gs, mus = [], []
+        for sp in spans:
+            al = sp["alpha_db_km"] / (10 / math.log(10))
+            X = B * ptot * sp["cr_w_km_thz"] * (1 - math.exp(-al * sp["length_km"])) / al
+            Gs.append({x: _srs_gain_eq14(X, x, B) for x in (a, b, c, x3)})
+            mus.append(oracle.mu(sp, ptot, B, a, b, c, "segment"))
+        chi1 = oracle.phase_coef(spans[0]["beta2_ps2_km"], spans[0]["beta3_ps3_km"], a, b, c)
+        ref = (spans[0]["gamma_w_km"] * mus[0] * math.sqrt(Gs[0][c] * Gs[1][c])
+               + spans[1]["gamma_w_km"] * mus[1] * np.exp(1j * chi1 * spans[0]["length_km"])
+               * math.sqrt(Gs[0][a] * Gs[0][b] * Gs[0][x3] * Gs[1][c]))
+        got = oracle.upsilon(spans, ptot, B, a, b, c, "segment", gain_mode=oracle.GAIN_LOSS_ONLY)
+        assert abs(got - ref) <= 1e-9 * abs(ref), (a, b, c, got, ref)
+
+
+def test_outer_frequency_rule_converges_second_order():
+    """n_f > 1: sigma^2 = (Rs / n_f) sum_n G(f_n) at the midpoints
+    f_n = -Rs/2 + (n + 1/2) Rs / n_f (Eq. 17's outer integral over the CUT).
+    It converges at second order to an adaptive 1-D integral of the same
+    PSD over [-Rs/2, Rs/2].  One channel, GN only: G(f) / G(0) = D(f) / D(0),
+    with D(f) the oracle's island integral at outer frequency f."""
+    rs, ro, N = 0.032, 0.5, 48
+    sp = W.spectrum_from(1, 0.05, rs, ro, [1e-3], ["gaussian"])
+    wl = W.Workload("t", sp, W.Link(W.make_spans([40.0], beta2=-21.7, beta3=0.14, cr=0.028)),
+                    W.Numerics(n_grid=N, egn=0), np.array([0]))
+    g0 = oracle.eval_cuts(wl, method="integral")["psd"][0, 0]
+    d0 = oracle.square_terms(wl, 0, 0, 0, f=0.0, method="integral")[1, 0]
+    integral, _ = si.quad(lambda f: oracle.square_terms(wl, 0, 0, 0, f=f, method="integral")[1, 0],
+                          -rs / 2, rs / 2, epsabs=0, epsrel=1e-11, limit=400)
+    exact = g0 / d0 * integral
+    errs = []
+    for n_f in (4, 8, 16):
+        r = oracle.eval_cuts(wl, method="integral", numerics=W.Numerics(n_grid=N, n_f=n_f, egn=0))
+        errs.append(abs(r["sigma2"][0] - exact) / exact)
+        # the PSD samples sit at the midpoints
+        f_mid = -rs / 2 + (np.arange(n_f) + 0.5) * rs / n_f
+        d = [oracle.square_terms(wl, 0, 0, 0, f=f, method="integral")[1, 0] for f in f_mid[:2]]
+        assert np.allclose(r["psd"][0, :2], g0 / d0 * np.array(d), rtol=1e-12)
+    ratios = [errs[i] / errs[i + 1] for i in range(len(errs) - 1)]
+    print("outer rule errors", errs, "ratios", ratios)
+    assert all(3.5 < q < 4.6 for q in ratios), (errs, ratios)
+
+
 def test_gaussian_formats_give_gn():
     wl = W.small_mixed(n_ch=5, n_spans=2, n_grid=10)
     wl.spectrum.phi[:] = 0.0
