@@ -32,7 +32,6 @@ constexpr int MAX_GRID = 8192;
 constexpr int MAX_NF = 4096;
 constexpr int MAX_CH = 100000;
 constexpr double TIE_TOL = 1e-9;                   // island-boundary tie tolerance in grid steps
-constexpr size_t DEFAULT_YCAP = size_t(8) << 30;   // coherent-sum buffer per launch chunk, bytes
 
 thread_local std::string g_create_error;
 
@@ -101,7 +100,7 @@ struct LinkInput {
 
 // Launch shape of the region kernel.
 struct Tuning {
-    int mode = 0;           // 0: one block per work unit, 1: persistent blocks on a queue
+    int mode = 1;           // 0: one block per work unit, 1: persistent blocks on a queue
     int blocks_per_cu = 0;  // queue mode; 0 = as many as fit
     int sort = 1;           // queue mode: cost-sorted order
     int spb = 0;            // slices per unit; 0 = automatic
@@ -119,14 +118,15 @@ struct Plan {
     std::vector<double> Sg, wt, s3;
     std::vector<int> livep;
     std::vector<int> runs;           // runs of PPT points by anti-diagonal (region kernel layout)
+    std::vector<int> adrun;          // [2N] first run of each anti-diagonal, then the run count
     std::vector<double> power, phi, psi;
     std::vector<InstDesc> insts;
     std::vector<SquareItem> items;
     std::vector<double> item_cost;   // per square: live points x (sum K + span count)
     std::vector<int> chunk_begin;    // square index where each launch chunk starts (+ end)
     std::vector<int> dlist;          // coherent-sum squares in square order
-    std::vector<int> dchunk_begin;
     std::vector<int> order;          // per chunk: cost-sorted permutation of its units
+    Tuning tu;                       // launch shape (queue mode whenever there are coherent sums)
     std::vector<std::vector<long long>> livepts;  // per link: [n_f][8 masks][2N] prefix of live points
     long long horner_steps = 0, live_points = 0;
     double alg_flop = 0;
@@ -136,15 +136,15 @@ struct Plan {
 
 // Device side of a plan.
 struct Workspace {
-    DevBuf links, spans, seg, Sg, wt, s3, livep, runs, insts, items, order, partD, partE, Y, dlist, counter, out,
-        power, phi, psi, sur;
+    DevBuf links, spans, seg, Sg, wt, s3, livep, runs, adrun, insts, items, order, partD, partE, eacc, dlist,
+        counter, out, power, phi, psi, sur;
     HostBuf stage;
     hipEvent_t ev_upload = nullptr;
     std::vector<hipEvent_t> ev_pool;
     void release()
     {
-        DevBuf* bufs[] = {&links, &spans, &seg, &Sg, &wt, &s3, &livep, &runs, &insts, &items, &order, &partD, &partE,
-                          &Y, &dlist, &counter, &out, &power, &phi, &psi, &sur};
+        DevBuf* bufs[] = {&links, &spans, &seg, &Sg, &wt, &s3, &livep, &runs, &adrun, &insts, &items, &order,
+                          &partD, &partE, &eacc, &dlist, &counter, &out, &power, &phi, &psi, &sur};
         for (DevBuf* b : bufs) b->release();
         stage.release();
         if (ev_upload) (void)hipEventDestroy(ev_upload);
@@ -174,7 +174,6 @@ struct isrs_ctx {
 
     bool profiling = false;
     isrs_stats stats{};
-    size_t ycap = DEFAULT_YCAP;
     int n_cu = 0;
 
     Workspace* ws = nullptr;
@@ -287,8 +286,11 @@ void plan_begin(const isrs_numerics* nu, Plan& p)
     p.AD = 2 * p.N - 1;
     // runs of PPT consecutive points along each anti-diagonal m = i + j
     p.runs.clear();
-    for (int m = 0; m < p.AD; ++m)
+    p.adrun.assign(1, 0);
+    for (int m = 0; m < p.AD; ++m) {
         for (int i = std::max(0, m - p.N + 1); i <= std::min(m, p.N - 1); i += PPT) p.runs.push_back(m << RUN_SHIFT | i);
+        p.adrun.push_back((int)p.runs.size());
+    }
     p.n_slices = (int)((p.runs.size() + THREADS - 1) / THREADS);
     p.fp32 = nu->precision == ISRS_PREC_FP32_PHASE64;
     p.mu_method = nu->mu_method;
@@ -481,7 +483,6 @@ void plan_link_work(const LinkInput& L, int link, const isrs_numerics* nu, const
                 it.inst = (int)p.insts.size();
                 it.k1 = k1;
                 it.k2 = k2;
-                it.y_slot = -1;
                 it.d_index = -1;
                 it.mult = explicit_sq ? 1.0f : (k1 < k2 ? 2.0f : 1.0f);
                 for (int l = -1; l <= 1; ++l) {
@@ -512,66 +513,60 @@ void plan_link_work(const LinkInput& L, int link, const isrs_numerics* nu, const
     }
 }
 
-// Launch chunks (bounded coherent-sum buffer), strip grouping and queue order.
-void plan_finish(Plan& p, size_t ycap, const Tuning& tu, int max_items = 0)
+// Coherent-sum rows, launch chunks (surrogate tables only), slice groups and
+// queue order.  A plan with coherent sums always runs on the queue: each of
+// its persistent blocks owns one accumulator slot.
+void plan_finish(Plan& p, const Tuning& tu, int max_items = 0)
 {
     p.seg32.resize(p.seg64.size());
     for (size_t i = 0; i < p.seg64.size(); ++i)
         p.seg32[i] = {(float)p.seg64[i].A, (float)p.seg64[i].zeta, (float)p.seg64[i].ratio, 0.0f};
-    const size_t ybytes = (size_t)p.N * p.N * (p.fp32 ? 8 : 16);
-    const size_t per_chunk = std::max<size_t>(1, ycap / std::max<size_t>(ybytes, 1));
     p.chunk_begin.assign(1, 0);
-    p.dchunk_begin.assign(1, 0);
     p.dlist.clear();
-    size_t slots = 0;
     for (size_t i = 0; i < p.items.size(); ++i) {
         SquareItem& it = p.items[i];
-        it.y_slot = -1;
         it.d_index = -1;
-        if (max_items > 0 && (int)i - p.chunk_begin.back() == max_items) {
-            p.chunk_begin.push_back((int)i);
-            p.dchunk_begin.push_back((int)p.dlist.size());
-            slots = 0;
-        }
+        if (max_items > 0 && (int)i - p.chunk_begin.back() == max_items) p.chunk_begin.push_back((int)i);
         if (it.egn_mask == 0) continue;
-        if (slots == per_chunk) {
-            p.chunk_begin.push_back((int)i);
-            p.dchunk_begin.push_back((int)p.dlist.size());
-            slots = 0;
-        }
-        it.y_slot = (int)slots++;
         it.d_index = (int)p.dlist.size();
         p.dlist.push_back((int)i);
     }
     p.chunk_begin.push_back((int)p.items.size());
-    p.dchunk_begin.push_back((int)p.dlist.size());
+    p.tu = tu;
+    if (!p.dlist.empty()) p.tu.mode = 1;
     // slice groups: by default enough units to fill the chip with few partials
     const long long n_items = (long long)p.items.size();
     int spb = tu.spb > 0 ? std::min(tu.spb, p.n_slices)
                          : (int)std::min<long long>(p.n_slices, std::max<long long>(1, n_items * p.n_slices / 32768));
     p.spb = spb;
     p.n_groups = (p.n_slices + spb - 1) / spb;
-    // queue order per chunk: longest units first (their cost splits evenly over groups)
+    // queue order per chunk: longest units first.  A square's cost splits
+    // evenly over its groups, except that a square with coherent sums runs
+    // whole in group 0 (its other groups are empty and go last).
     const size_t n_units = p.items.size() * p.n_groups;
     p.order.resize(n_units);
     std::iota(p.order.begin(), p.order.end(), 0);
-    if (tu.mode == 1 && tu.sort) {
+    if (p.tu.mode == 1 && p.tu.sort) {
         // stable bucket sort on a cost class (1/64 octave): the queue only needs
         // the longest units first, and the order stays deterministic
         constexpr int NB = 4096;
-        std::vector<uint16_t> cls(p.items.size());
-        for (size_t i = 0; i < p.items.size(); ++i) {
-            const double lc = 64.0 * std::log2(std::max(1.0, p.item_cost[i]));
-            cls[i] = (uint16_t)(NB - 1 - std::min<double>(NB - 1, std::floor(lc)));
-        }
+        auto cls = [&](size_t u) -> int {
+            const size_t i = u / p.n_groups;
+            double cost = p.item_cost[i] / p.n_groups;
+            if (p.items[i].egn_mask != 0) cost = (u % p.n_groups == 0) ? p.item_cost[i] : 0.0;
+            const double lc = 64.0 * std::log2(std::max(1.0, cost));
+            return (int)(NB - 1 - std::min<double>(NB - 1, std::floor(lc)));
+        };
+        std::vector<uint16_t> ucls(n_units);
+        for (size_t u = 0; u < n_units; ++u) ucls[u] = (uint16_t)cls(u);
         std::vector<int> tmp;
         for (size_t ch = 0; ch + 1 < p.chunk_begin.size(); ++ch) {
             const size_t b = (size_t)p.chunk_begin[ch] * p.n_groups, e = (size_t)p.chunk_begin[ch + 1] * p.n_groups;
             std::vector<size_t> start(NB + 1, 0);
-            for (size_t u = b; u < e; ++u) start[cls[u / p.n_groups] + 1]++;
+            for (size_t u = b; u < e; ++u) start[ucls[u] + 1]++;
             for (int k = 0; k < NB; ++k) start[k + 1] += start[k];
             tmp.resize(e - b);
-            for (size_t u = b; u < e; ++u) tmp[start[cls[u / p.n_groups]]++] = (int)u;
+            for (size_t u = b; u < e; ++u) tmp[start[ucls[u]]++] = (int)u;
             std::copy(tmp.begin(), tmp.end(), p.order.begin() + b);
         }
     }
@@ -631,16 +626,25 @@ std::string plan_check(const Plan& p)
     }
     for (int r : p.runs)
         if ((r >> RUN_SHIFT) >= p.AD || (r & RUN_MASK) >= p.N) return "run out of the grid";
+    if (p.adrun.size() != (size_t)p.AD + 1 || p.adrun.back() != (int)p.runs.size()) return "anti-diagonal run table";
+    for (int m = 0; m < p.AD; ++m)
+        if (p.adrun[m] >= p.adrun[m + 1] || (p.runs[p.adrun[m]] >> RUN_SHIFT) != m ||
+            (p.runs[p.adrun[m]] & RUN_MASK) != std::max(0, m - p.N + 1))
+            return "anti-diagonal run table";
+    if (!p.dlist.empty() && (p.tu.mode != 1 || p.queue_blocks < 1)) return "coherent sums need the queue";
+    for (size_t d = 0; d < p.dlist.size(); ++d)
+        if (p.dlist[d] < 0 || p.dlist[d] >= (int)p.items.size() || p.items[p.dlist[d]].d_index != (int)d)
+            return "coherent-sum list";
     return "";
 }
 
 // Persistent grid of a queue launch (occupancy query: never inside a capture).
-void plan_queue_shape(const isrs_ctx* c, const Tuning& tu, Plan& p)
+void plan_queue_shape(const isrs_ctx* c, Plan& p)
 {
     p.queue_blocks = 0;
-    if (tu.mode != 1) return;
+    if (p.tu.mode != 1) return;
     const int per_cu = region_blocks_per_cu(p.fp32, p.mu_method);
-    p.queue_blocks = std::max(1, c->n_cu) * (tu.blocks_per_cu > 0 ? std::min(tu.blocks_per_cu, per_cu) : per_cu);
+    p.queue_blocks = std::max(1, c->n_cu) * (p.tu.blocks_per_cu > 0 ? std::min(p.tu.blocks_per_cu, per_cu) : per_cu);
 }
 
 int32_t plan_upload(isrs_ctx* c, Workspace& w, const Plan& p, hipStream_t st)
@@ -649,7 +653,7 @@ int32_t plan_upload(isrs_ctx* c, Workspace& w, const Plan& p, hipStream_t st)
     if (!bad.empty()) return fail(c, ISRS_E_ARG, "internal plan check: " + bad);
     if (w.ev_upload) HIP_TRY(c, hipEventSynchronize(w.ev_upload));  // previous copies out of staging
     const size_t need = staged(p.links) + staged(p.spans) + (p.fp32 ? staged(p.seg32) : staged(p.seg64)) +
-                        staged(p.Sg) + staged(p.wt) + staged(p.s3) + staged(p.livep) + staged(p.runs) + staged(p.insts) +
+                        staged(p.Sg) + staged(p.wt) + staged(p.s3) + staged(p.livep) + staged(p.runs) + staged(p.adrun) + staged(p.insts) +
                         staged(p.items) + staged(p.dlist) + staged(p.order) + staged(p.power) + staged(p.phi) +
                         staged(p.psi);
     HIP_TRY(c, w.stage.ensure(need));
@@ -667,6 +671,7 @@ int32_t plan_upload(isrs_ctx* c, Workspace& w, const Plan& p, hipStream_t st)
     if ((rc = upload(c, st, w.s3, p.s3, stage))) return rc;
     if ((rc = upload(c, st, w.livep, p.livep, stage))) return rc;
     if ((rc = upload(c, st, w.runs, p.runs, stage))) return rc;
+    if ((rc = upload(c, st, w.adrun, p.adrun, stage))) return rc;
     if ((rc = upload(c, st, w.insts, p.insts, stage))) return rc;
     if ((rc = upload(c, st, w.items, p.items, stage))) return rc;
     if ((rc = upload(c, st, w.dlist, p.dlist, stage))) return rc;
@@ -679,11 +684,7 @@ int32_t plan_upload(isrs_ctx* c, Workspace& w, const Plan& p, hipStream_t st)
 
     HIP_TRY(c, w.partD.ensure(std::max<size_t>(1, p.items.size()) * p.n_groups * 3 * sizeof(double)));
     HIP_TRY(c, w.partE.ensure(std::max<size_t>(1, p.dlist.size()) * 12 * sizeof(double)));
-    size_t max_slots = 0;
-    for (size_t ch = 0; ch + 1 < p.dchunk_begin.size(); ++ch)
-        max_slots = std::max<size_t>(max_slots, p.dchunk_begin[ch + 1] - p.dchunk_begin[ch]);
-    const size_t ybytes = (size_t)p.N * p.N * (p.fp32 ? 8 : 16);
-    HIP_TRY(c, w.Y.ensure(std::max<size_t>(1, max_slots) * ybytes));
+    if (!p.dlist.empty()) HIP_TRY(c, w.eacc.ensure((size_t)p.queue_blocks * eslot(p.N) * sizeof(double2)));
     HIP_TRY(c, w.counter.ensure(sizeof(int) * std::max<size_t>(1, p.chunk_begin.size())));
     return ISRS_OK;
 }
@@ -699,11 +700,11 @@ hipEvent_t pool_event(Workspace& w, size_t i)
 }
 
 struct Timings {
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> reg, egn, asm_;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> reg, asm_;
 };
 
 // Stream-ordered launches of a plan (graph-capturable when timing is off).
-int32_t plan_enqueue(isrs_ctx* c, Workspace& w, const Plan& p, const Tuning& tu, hipStream_t st, double* eta_d,
+int32_t plan_enqueue(isrs_ctx* c, Workspace& w, const Plan& p, hipStream_t st, double* eta_d,
                      double* s2_d, double* terms_d, double* psd_d, bool assemble, Timings* tm,
                      SurrogateFill* sf = nullptr, float* sur_tab = nullptr)
 {
@@ -718,7 +719,9 @@ int32_t plan_enqueue(isrs_ctx* c, Workspace& w, const Plan& p, const Tuning& tu,
     ra.insts = w.insts.as<InstDesc>();
     ra.items = w.items.as<SquareItem>();
     ra.partD = w.partD.as<double>();
-    ra.ybuf = w.Y.p;
+    ra.partE = w.partE.as<double>();
+    ra.eacc = p.dlist.empty() ? nullptr : w.eacc.as<double2>();
+    ra.adrun = w.adrun.as<int>();
     ra.n_groups = p.n_groups;
     ra.spb = p.spb;
     ra.n_slices = p.n_slices;
@@ -727,21 +730,10 @@ int32_t plan_enqueue(isrs_ctx* c, Workspace& w, const Plan& p, const Tuning& tu,
     ra.N = p.N;
     ra.mu_method = p.mu_method;
     int blocks = 0;
-    if (tu.mode == 1) {
+    if (p.tu.mode == 1) {
         blocks = p.queue_blocks;  // fixed at plan time, outside any stream capture
         ra.order = w.order.as<int>();
     }
-
-    EgnArgs ea{};
-    ea.links = ra.links;
-    ea.Sg = ra.Sg;
-    ea.wt = ra.wt;
-    ea.s3 = ra.s3;
-    ea.insts = ra.insts;
-    ea.items = ra.items;
-    ea.ybuf = w.Y.p;
-    ea.partE = w.partE.as<double>();
-    ea.N = p.N;
 
     size_t ev_i = 0;
     using EvList = std::vector<std::pair<hipEvent_t, hipEvent_t>>;
@@ -757,7 +749,6 @@ int32_t plan_enqueue(isrs_ctx* c, Workspace& w, const Plan& p, const Tuning& tu,
         return ISRS_OK;
     };
     EvList* ev_reg = tm ? &tm->reg : nullptr;
-    EvList* ev_egn = tm ? &tm->egn : nullptr;
     EvList* ev_asm = tm ? &tm->asm_ : nullptr;
     int32_t rc;
     const size_t n_chunks = p.chunk_begin.size() - 1;
@@ -765,7 +756,7 @@ int32_t plan_enqueue(isrs_ctx* c, Workspace& w, const Plan& p, const Tuning& tu,
         const int b = p.chunk_begin[ch], e = p.chunk_begin[ch + 1];
         ra.unit0 = b * p.n_groups;
         ra.n_units = (e - b) * p.n_groups;
-        if (tu.mode == 1) {
+        if (p.tu.mode == 1) {
             ra.counter = w.counter.as<int>() + ch;
             HIP_TRY(c, launch_zero_counter(ra.counter, st));
         }
@@ -777,13 +768,6 @@ int32_t plan_enqueue(isrs_ctx* c, Workspace& w, const Plan& p, const Tuning& tu,
         if ((rc = mark(ev_reg, true))) return rc;
         HIP_TRY(c, launch_region(ra, blocks, p.fp32, st));
         if ((rc = mark(ev_reg, false))) return rc;
-        const int db = p.dchunk_begin[ch], de = p.dchunk_begin[ch + 1];
-        if (de > db) {
-            ea.dlist = w.dlist.as<int>() + db;
-            if ((rc = mark(ev_egn, true))) return rc;
-            HIP_TRY(c, launch_egn(ea, de - db, p.fp32, st));
-            if ((rc = mark(ev_egn, false))) return rc;
-        }
     }
     if (assemble) {
         AssembleArgs aa{};
@@ -791,7 +775,7 @@ int32_t plan_enqueue(isrs_ctx* c, Workspace& w, const Plan& p, const Tuning& tu,
         aa.insts = ra.insts;
         aa.items = ra.items;
         aa.partD = ra.partD;
-        aa.partE = ea.partE;
+        aa.partE = ra.partE;
         aa.power = w.power.as<double>();
         aa.phi = w.phi.as<double>();
         aa.psi = w.psi.as<double>();
@@ -823,7 +807,7 @@ int32_t collect_timings(isrs_ctx* c, Timings& tm)
     };
     int32_t rc;
     if ((rc = sum(tm.reg, c->stats.region_ms))) return rc;
-    if ((rc = sum(tm.egn, c->stats.egn_ms))) return rc;
+    c->stats.egn_ms = 0.0;  // the coherent sums run inside the region kernel
     if ((rc = sum(tm.asm_, c->stats.assemble_ms))) return rc;
     return ISRS_OK;
 }
@@ -934,8 +918,8 @@ int32_t evaluate(isrs_ctx* c, const isrs_numerics* nu, const int32_t* cuts, int 
             plan_link_tables(Lg, &ng, p);
             plan_link_work(Lg, (int)g, &ng, kappa12, m_explicit, p);
         }
-        plan_finish(p, c->ycap, tu, max_items);
-        plan_queue_shape(c, tu, p);
+        plan_finish(p, tu, max_items);
+        plan_queue_shape(c, p);
     } catch (const std::bad_alloc&) {
         return fail(c, ISRS_E_NOMEM, "host allocation failed");
     }
@@ -945,7 +929,7 @@ int32_t evaluate(isrs_ctx* c, const isrs_numerics* nu, const int32_t* cuts, int 
     if (sf) HIP_TRY(c, w.sur.ensure((size_t)max_items * p.N * p.N * p.links[0].n_sp * sizeof(float)));
     auto t1 = std::chrono::steady_clock::now();
     Timings tm;
-    if ((rc = plan_enqueue(c, w, p, tu, c->stream, eta_d, s2_d, terms_d, psd_d, partials_host == nullptr,
+    if ((rc = plan_enqueue(c, w, p, c->stream, eta_d, s2_d, terms_d, psd_d, partials_host == nullptr,
                            c->profiling ? &tm : nullptr, sf, sf ? w.sur.as<float>() : nullptr)))
         return rc;
     if (partials_host) {
@@ -1056,8 +1040,8 @@ int32_t batch_plan(isrs_ctx* c, isrs_batch* b, const isrs_numerics* nu)
         p.item_cost.reserve(est);
         for (int l = 0; l < b->n_links; ++l) plan_link_tables(b->link(l), nu, p);
         for (int l = 0; l < b->n_links; ++l) plan_link_work(b->link(l), l, nu, nullptr, 0, p);
-        plan_finish(p, c->ycap, b->tuning);
-        plan_queue_shape(c, b->tuning, p);
+        plan_finish(p, b->tuning);
+        plan_queue_shape(c, p);
     } catch (const std::bad_alloc&) {
         return fail(c, ISRS_E_NOMEM, "host allocation failed");
     }
@@ -1080,7 +1064,7 @@ int32_t batch_run(isrs_ctx* c, isrs_batch* b, double* eta_d, bool use_graph)
     if (c->profiling || !use_graph || !b->warm) {
         b->warm = true;
         Timings tm;
-        int32_t rc = plan_enqueue(c, b->ws, b->plan, b->tuning, c->stream, eta_d, nullptr, nullptr, nullptr, true,
+        int32_t rc = plan_enqueue(c, b->ws, b->plan, c->stream, eta_d, nullptr, nullptr, nullptr, true,
                                   c->profiling ? &tm : nullptr);
         if (rc) return rc;
         record_stats(c, b->plan, 0.0, c->profiling);
@@ -1089,7 +1073,7 @@ int32_t batch_run(isrs_ctx* c, isrs_batch* b, double* eta_d, bool use_graph)
     }
     if (!b->exec) {
         HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-        int32_t rc = plan_enqueue(c, b->ws, b->plan, b->tuning, c->stream, b->out.as<double>(), nullptr, nullptr,
+        int32_t rc = plan_enqueue(c, b->ws, b->plan, c->stream, b->out.as<double>(), nullptr, nullptr,
                                   nullptr, true, nullptr);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(c->stream, &g);
@@ -1728,9 +1712,10 @@ int32_t isrs_batch_get_tuning(const isrs_batch* b, int32_t* mode, int32_t* bpc, 
 {
     try {
         if (!b) return ISRS_E_ARG;
-        if (mode) *mode = b->tuning.mode;
-        if (bpc) *bpc = b->tuning.blocks_per_cu;
-        if (sort) *sort = b->tuning.sort;
+        const Tuning& t = b->planned ? b->plan.tu : b->tuning;
+        if (mode) *mode = t.mode;
+        if (bpc) *bpc = t.blocks_per_cu;
+        if (sort) *sort = t.sort;
         if (slices) *slices = b->planned ? b->plan.spb : b->tuning.spb;
         return ISRS_OK;
     } catch (...) {
@@ -1786,7 +1771,7 @@ int32_t isrs_autotune(isrs_ctx* c, isrs_batch* b, const isrs_numerics* nu, const
                 c->profiling = prof;
                 return rc;
             }
-            const double ms = c->stats.region_ms + c->stats.egn_ms;
+            const double ms = c->stats.region_ms;
             if (ms < best) {
                 best = ms;
                 best_t = t;

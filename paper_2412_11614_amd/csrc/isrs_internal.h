@@ -89,21 +89,29 @@ struct InstDesc {
     int sq_end;
 };
 
+// Coherent-sum accumulators of one persistent block, in complex FP64: row
+// sums [3 islands][N] (E), column sums [3][N] (F), anti-diagonal sums [2N]
+// (G and H).
+__host__ __device__ constexpr size_t eslot(int N) { return (size_t)8 * N; }
+
 // One channel-pair square of the (f1 <-> f2 folded) work list.
 struct SquareItem {
     int inst;
     int k1, k2;
     int lmask;       // bit (l+1): island l has a valid third channel and live points
     int egn_mask;    // bit 4*(l+1) + t, t = 0 E (rows), 1 F (columns), 2 G (anti-diagonals), 3 H (full)
-    int y_slot;      // slot in the chunk's Upsilon buffer, -1 if no coherent sums are needed
+    int pad_;
     int d_index;     // row in the coherent-sum results, -1 if none
     float mult;      // 2 for k1 < k2 (mirror square folded in), else 1
 };
 
 // A launch covers work units [unit0, unit0 + n_units); unit u is slice group
-// u % n_groups of square u / n_groups.  With a queue, blocks pop positions
-// from *counter and run unit order[unit0 + pos] (a cost-sorted permutation of
-// the launch's units); without one, block b runs unit unit0 + b.
+// u % n_groups of square u / n_groups.  A square with coherent sums
+// (egn_mask != 0) is run whole by its group 0, whose block keeps the sums in
+// its accumulator slot; its other groups only write zero partials.  With a
+// queue, blocks pop positions from *counter and run unit order[unit0 + pos]
+// (a cost-sorted permutation of the launch's units); without one, block b
+// runs unit unit0 + b (only for plans without coherent sums).
 struct RegionArgs {
     const LinkDesc* links;
     const SpanConst* spans;
@@ -115,7 +123,9 @@ struct RegionArgs {
     const InstDesc* insts;
     const SquareItem* items;
     double* partD;            // [units][3]
-    void* ybuf;               // Upsilon of the chunk's coherent-sum squares, [slot][N][N] complex
+    double* partE;            // [coherent-sum squares][3 islands][E, F, G, H]
+    double2* eacc;            // coherent-sum accumulators, one slot of eslot(N) complex per persistent block
+    const int* adrun;         // [2N] first run of each anti-diagonal (run table index), then the run count
     const int* order;         // queue mode: permutation of units, else null
     int* counter;             // queue mode: head counter (zeroed before the launch)
     int unit0;
@@ -129,19 +139,6 @@ struct RegionArgs {
     int mu_method;            // MU_SEG, MU_MAC, MU_INT or MU_SUR
     const float* sur_tab;     // MU_SUR: ln(|mu|^2 / |eta_6|^2) per (point, span), NaN = closed form;
     int sur_item0;            //   row ((item - sur_item0) * N + j) * N + i) * n_sp + s
-};
-
-struct EgnArgs {
-    const LinkDesc* links;
-    const double* Sg;
-    const double* wt;
-    const double* s3;
-    const InstDesc* insts;
-    const SquareItem* items;
-    const int* dlist;         // chunk's coherent-sum squares (item indices)
-    const void* ybuf;
-    double* partE;            // [n_delta][3][4]
-    int N;
 };
 
 struct AssembleArgs {
@@ -166,7 +163,6 @@ struct AssembleArgs {
 // unit; blocks > 0 launches that many persistent blocks on the queue.
 hipError_t launch_region(const RegionArgs& a, int blocks, bool fp32, hipStream_t st);
 hipError_t launch_zero_counter(int* counter, hipStream_t st);
-hipError_t launch_egn(const EgnArgs& a, int n_delta, bool fp32, hipStream_t st);
 hipError_t launch_assemble(const AssembleArgs& a, hipStream_t st);
 int region_blocks_per_cu(bool fp32, int mu_method);
 

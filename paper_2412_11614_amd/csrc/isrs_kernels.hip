@@ -209,6 +209,152 @@ __device__ __forceinline__ void node_weight(int n, const R (&mr)[4], const R (&m
     }
 }
 
+// Coherent sums of one slice of a square with format terms (Eqs. 18-21,
+// restructured so that each inner integral is a row, column or anti-diagonal
+// sum of Upsilon).  The slice's Upsilon goes through LDS (over the staged gain
+// rows, which are no longer read); every row, column and anti-diagonal the
+// slice touches adds its part, summed in a fixed order, to the block's
+// accumulator slot in FP64.  Row and column j belong to thread j mod THREADS,
+// anti-diagonal m to thread m mod THREADS, in every slice and square, so no
+// two threads ever touch one accumulator and the result is deterministic.
+template <typename R>
+__device__ void egn_slice(const int em, const int N, const int c0, const int c1, const int mlo, const int mhi,
+                          const int m, const int i0, const int ihi, const bool has, const R (&ur)[PPT],
+                          const R (&ui)[PPT], const double* Sg, const double* wt, const double* s3,
+                          const int* __restrict__ adrun, void* lds, double2* acc)
+{
+    using V2 = typename Prec<R>::V2;
+    const int tid = threadIdx.x, AD = 2 * N - 1, nrows = mhi - mlo + 1;
+    V2* ys = reinterpret_cast<V2*>(lds);                           // [THREADS * PPT] Upsilon by run position
+    double2* rp = reinterpret_cast<double2*>(ys + THREADS * PPT);  // [THREADS] per run: sum of S1 S2 Upsilon
+    double* ws = reinterpret_cast<double*>(rp + THREADS);          // [3][NAD] island weight * S(f3)
+    int* adr = reinterpret_cast<int*>(ws + 3 * NAD);               // [NAD + 1] first run of each anti-diagonal
+    const bool need_ad = (em & 0xCCC) != 0;
+    __syncthreads();
+    double gr = 0.0, gi = 0.0;
+#pragma unroll
+    for (int r = 0; r < PPT; ++r) {
+        const int ip = i0 + r;
+        const bool ok = has && ip <= ihi;
+        ys[tid * PPT + r] = ok ? V2{ur[r], ui[r]} : V2{R(0), R(0)};
+        if (ok && need_ad) {
+            const double w = Sg[ip] * Sg[m - ip];
+            gr += w * (double)ur[r];
+            gi += w * (double)ui[r];
+        }
+    }
+    rp[tid] = double2{gr, gi};
+    if (tid <= nrows) {
+        adr[tid] = adrun[mlo + tid];
+        if (tid < nrows)
+            for (int l = 0; l < 3; ++l) ws[l * NAD + tid] = wt[l * AD + mlo + tid] * s3[l * AD + mlo + tid];
+    }
+    __syncthreads();
+    // rows and columns the slice touches: [lo, hi]; this thread's first one
+    const int lo = max(0, mlo - (N - 1)), hi = min(N - 1, mhi);
+    const int first = lo + ((tid - lo) % THREADS + THREADS) % THREADS;
+    // E (t = 0): row j, the sum over i of w S1 S3 Upsilon (Eq. 18);
+    // F (t = 1): column i, the sum over j of w S2 S3 Upsilon (Eq. 19)
+    for (int lt = 0; lt < 6; ++lt) {
+        const int l = lt >> 1, t = lt & 1;
+        if (!((em >> (4 * l + t)) & 1)) continue;
+        double2* dst = acc + (3 * t + l) * N;
+        for (int x = first; x <= hi; x += THREADS) {
+            double cr = 0.0, ci = 0.0;
+            for (int q = 0; q < nrows; ++q) {
+                const int mm = mlo + q, other = mm - x;   // the point's other index
+                if (other < 0 || other >= N) continue;
+                const int i = t ? x : other;
+                const int off = i - max(0, mm - (N - 1));
+                const int run = adr[q] + off / PPT;
+                if (run < c0 || run > c1) continue;
+                const V2 y = ys[(run - c0) * PPT + off % PPT];
+                const double w = ws[l * NAD + q] * Sg[other];
+                cr += w * (double)y.x;
+                ci += w * (double)y.y;
+            }
+            double2 v = dst[x];
+            v.x += cr;
+            v.y += ci;
+            dst[x] = v;
+        }
+    }
+    // G and H: anti-diagonal m, sum of S1 S2 Upsilon (Eqs. 20, 21)
+    if (need_ad) {
+        const int q = ((tid - mlo) % THREADS + THREADS) % THREADS;
+        if (q < nrows) {
+            const int rb = max(c0, adr[q]), re = min(c1 + 1, adr[q + 1]);
+            double sr = 0.0, si = 0.0;
+            for (int run = rb; run < re; ++run) {
+                sr += rp[run - c0].x;
+                si += rp[run - c0].y;
+            }
+            double2 v = acc[6 * N + mlo + q];
+            v.x += sr;
+            v.y += si;
+            acc[6 * N + mlo + q] = v;
+        }
+    }
+}
+
+// The format terms of a square from its accumulated sums (bare, grid weights
+// included):
+//   E_l = h^3 sum_j S2^2 |row_l(j)|^2,  F_l = h^3 sum_i S1^2 |col_l(i)|^2,
+//   G_l = h^3 sum_m w_l S3_l^2 |ad(m)|^2,  H_l = h^4 |sum_m w_l S3_l ad(m)|^2.
+__device__ void egn_finish(const int em, const int N, const double h, const double* Sg, const double* wt,
+                           const double* s3, const double2* acc, double* red, double* out)
+{
+    const int tid = threadIdx.x, AD = 2 * N - 1;
+    const double h3 = h * h * h;
+    double res[3][4];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        res[l][0] = res[l][1] = res[l][2] = res[l][3] = 0.0;
+        if ((em >> (4 * l)) & 1) {
+            double v = 0.0;
+            for (int j = tid; j < N; j += THREADS) {
+                const double2 e = acc[l * N + j];
+                v += Sg[j] * Sg[j] * (e.x * e.x + e.y * e.y);
+            }
+            res[l][0] = h3 * block_sum(v, red);
+        }
+        if ((em >> (4 * l + 1)) & 1) {
+            double v = 0.0;
+            for (int i = tid; i < N; i += THREADS) {
+                const double2 e = acc[(3 + l) * N + i];
+                v += Sg[i] * Sg[i] * (e.x * e.x + e.y * e.y);
+            }
+            res[l][1] = h3 * block_sum(v, red);
+        }
+        if ((em >> (4 * l + 2)) & 1) {
+            double v = 0.0;
+            for (int mm = tid; mm < AD; mm += THREADS) {
+                const double2 e = acc[6 * N + mm];
+                const double w3 = s3[l * AD + mm];
+                v += wt[l * AD + mm] * w3 * w3 * (e.x * e.x + e.y * e.y);
+            }
+            res[l][2] = h3 * block_sum(v, red);
+        }
+        if ((em >> (4 * l + 3)) & 1) {
+            double vr = 0.0, vi = 0.0;
+            for (int mm = tid; mm < AD; mm += THREADS) {
+                const double2 e = acc[6 * N + mm];
+                const double w = wt[l * AD + mm] * s3[l * AD + mm];
+                vr += w * e.x;
+                vi += w * e.y;
+            }
+            const double xr = block_sum(vr, red), xi = block_sum(vi, red);
+            res[l][3] = h3 * h * (xr * xr + xi * xi);
+        }
+    }
+    if (tid == 0) {
+#pragma unroll
+        for (int l = 0; l < 3; ++l)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) out[l * 4 + t] = res[l][t];
+    }
+}
+
 // One work unit: slice group u % n_groups of square u / n_groups.  The
 // square's points are cut into runs of PPT consecutive points along an
 // anti-diagonal (f1 + f2 constant), ordered by anti-diagonal; a slice is
@@ -219,12 +365,11 @@ __device__ __forceinline__ void node_weight(int n, const R (&mr)[4], const R (&m
 // parameters: nothing the kernel writes aliases them, so their block-uniform
 // reads go through scalar loads.
 template <typename R, int MU>
-__device__ void region_unit(const RegionArgs& a, const int u, VecOf<R>* g_vec, double* red,
+__device__ void region_unit(const RegionArgs& a, const int u, const int slot, VecOf<R>* g_vec, double* red,
                             const SpanConst* __restrict__ spans_all, const int* __restrict__ runs,
                             const int* __restrict__ livep_all)
 {
     using P = Prec<R>;
-    using V2 = typename P::V2;
     using Vec = typename P::Vec;
     using Seg = typename P::Seg;
     constexpr int KC = P::KC, KP = P::KP, VW = P::VW, KPV = KP / VW;
@@ -252,11 +397,23 @@ __device__ void region_unit(const RegionArgs& a, const int u, VecOf<R>* g_vec, d
     const double* Sg = a.Sg + lk.sg0;
     const SpanConst* spans = spans_all + lk.span0;
     const Seg* seg = reinterpret_cast<const Seg*>(a.seg);
-    V2* ybuf = it.y_slot >= 0 ? reinterpret_cast<V2*>(a.ybuf) + (size_t)it.y_slot * N * N : nullptr;
     double dacc[3] = {0.0, 0.0, 0.0};
 
-    const int sl_end = min(a.n_slices, (grp + 1) * a.spb);
-    for (int sl = grp * a.spb; sl < sl_end; ++sl) {
+    // a square with coherent sums runs whole in group 0 (its other groups add
+    // nothing), with the sums in this block's accumulator slot
+    int sl_begin = grp * a.spb, sl_end = min(a.n_slices, (grp + 1) * a.spb);
+    double2* acc = nullptr;
+    if (it.egn_mask != 0) {
+        sl_end = sl_begin;
+        if (grp == 0 && slot >= 0) {
+            sl_begin = 0;
+            sl_end = a.n_slices;
+            acc = a.eacc + (size_t)slot * eslot(N);
+            for (int j = tid; j < 6 * N; j += THREADS) acc[j] = double2{0.0, 0.0};
+            for (int mm = tid; mm < AD; mm += THREADS) acc[6 * N + mm] = double2{0.0, 0.0};
+        }
+    }
+    for (int sl = sl_begin; sl < sl_end; ++sl) {
         const int c0 = sl * THREADS;
         const int c1 = min(c0 + THREADS, a.n_runs) - 1;       // last run of the slice
         const int mlo = runs[c0] >> RUN_SHIFT, mhi = runs[c1] >> RUN_SHIFT;
@@ -270,14 +427,7 @@ __device__ void region_unit(const RegionArgs& a, const int u, VecOf<R>* g_vec, d
 #pragma unroll
         for (int l = 0; l < 3; ++l)
             if ((it.lmask >> l) & 1) live |= livep[l * (AD + 1) + mhi + 1] - livep[l * (AD + 1) + mlo] > 0;
-        if (!live) {
-            if (ybuf && has) {
-#pragma unroll
-                for (int r = 0; r < PPT; ++r)
-                    if (i0 + r <= ihi) ybuf[(size_t)(m - i0 - r) * N + i0 + r] = V2{R(0), R(0)};
-            }
-            continue;
-        }
+        if (!live) continue;
 
         // per point d12 = (f1 - f)(f2 - f) in FP64; a + b and f3 are the run's
         const double ssum = sb + (m + 1 - N) * h;
@@ -498,7 +648,11 @@ __device__ void region_unit(const RegionArgs& a, const int u, VecOf<R>* g_vec, d
             }
         }
 
-        // GN island sums (Eq. 17) and the coherent-sum buffer
+        if (acc)
+            egn_slice<R>(it.egn_mask, N, c0, c1, mlo, mhi, m, i0, ihi, has, ur, ui, Sg, wt, s3, a.adrun, g_vec,
+                         acc);
+
+        // GN island sums (Eq. 17)
         if (!has) continue;
         double vs = 0.0;
 #pragma unroll
@@ -508,7 +662,6 @@ __device__ void region_unit(const RegionArgs& a, const int u, VecOf<R>* g_vec, d
             const double S1 = Sg[ip], S2 = Sg[m - ip];
             const double u2 = (double)ur[r] * (double)ur[r] + (double)ui[r] * (double)ui[r];
             vs += S1 * S1 * S2 * S2 * u2;
-            if (ybuf) ybuf[(size_t)(m - ip) * N + ip] = V2{ur[r], ui[r]};
         }
 #pragma unroll
         for (int l = 0; l < 3; ++l)
@@ -523,6 +676,7 @@ __device__ void region_unit(const RegionArgs& a, const int u, VecOf<R>* g_vec, d
         const double v = block_sum(dacc[l], red);
         if (tid == 0) out[l] = v;
     }
+    if (acc) egn_finish(it.egn_mask, N, h, Sg, wt, s3, acc, red, a.partE + (size_t)it.d_index * 12);
 }
 
 // Waves per SIMD the register budget is set for: FP32 at most 128 VGPRs (four
@@ -542,7 +696,10 @@ __global__ void __launch_bounds__(THREADS, (region_min_waves<R, MU>())) region_k
 {
     __shared__ VecOf<R> g_vec[NAD * (Prec<R>::KP / Prec<R>::VW)];
     __shared__ double red[THREADS / 64];
-    region_unit<R, MU>(a, a.unit0 + blockIdx.x, g_vec, red, spans, runs, livep);
+    static_assert(sizeof(g_vec) >= THREADS * PPT * sizeof(typename Prec<R>::V2) + THREADS * sizeof(double2) +
+                                       3 * NAD * sizeof(double) + (NAD + 1) * sizeof(int),
+                  "the coherent-sum staging must fit in the gain rows");
+    region_unit<R, MU>(a, a.unit0 + blockIdx.x, -1, g_vec, red, spans, runs, livep);
 }
 
 // Persistent blocks on a queue: every block pops unit positions until the
@@ -563,7 +720,7 @@ __global__ void __launch_bounds__(THREADS, (region_min_waves<R, MU>())) region_q
         const int pos = pos_s;
         __syncthreads();
         if (pos < 0 || pos >= a.n_units) break;
-        region_unit<R, MU>(a, a.order[a.unit0 + pos], g_vec, red, spans, runs, livep);
+        region_unit<R, MU>(a, a.order[a.unit0 + pos], blockIdx.x, g_vec, red, spans, runs, livep);
     }
 }
 
@@ -572,137 +729,6 @@ __global__ void __launch_bounds__(THREADS, (region_min_waves<R, MU>())) region_q
 __global__ void zero_counter_kernel(int* c)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) atomicExch(c, 0);
-}
-
-// Coherent sums of one square for the format terms (bare, grid weights included):
-//   E_l = h^3 sum_j S2^2 |sum_i w S1 S3 U|^2      (rows,  Eq. 18)
-//   F_l = h^3 sum_i S1^2 |sum_j w S2 S3 U|^2      (columns, Eq. 19)
-//   G_l = h^3 sum_m w S3^2 |sum_{i+j=m} S1 S2 U|^2 (anti-diagonals, Eq. 20)
-//   H_l = h^4 |sum_ij w S1 S2 S3 U|^2            (Eq. 21)
-template <typename R>
-__global__ void __launch_bounds__(THREADS) egn_kernel(EgnArgs a)
-{
-    using V2 = typename Prec<R>::V2;
-    __shared__ double red[THREADS / 64];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int item = a.dlist[blockIdx.x];
-    const SquareItem it = a.items[item];
-    const InstDesc in = a.insts[it.inst];
-    const LinkDesc lk = a.links[in.link];
-    const int N = a.N, AD = 2 * N - 1;
-    const double h = lk.h;
-    const double* wt = a.wt + lk.tab0 + (size_t)in.nf_idx * 3 * AD;
-    const double* s3 = a.s3 + lk.tab0 + (size_t)in.nf_idx * 3 * AD;
-    const V2* Y = reinterpret_cast<const V2*>(a.ybuf) + (size_t)it.y_slot * N * N;
-    const double* Sg = a.Sg + lk.sg0;
-    const int em = it.egn_mask;
-    double res[3][4];
-#pragma unroll
-    for (int l = 0; l < 3; ++l)
-#pragma unroll
-        for (int t = 0; t < 4; ++t) res[l][t] = 0.0;
-
-    // E: rows, one wave per row
-    if (em & 0x111) {
-        double e[3] = {0.0, 0.0, 0.0};
-        for (int j = wave; j < N; j += THREADS / 64) {
-            double cr[3] = {0, 0, 0}, ci[3] = {0, 0, 0};
-            for (int i = lane; i < N; i += 64) {
-                const V2 y = Y[(size_t)j * N + i];
-                const int m = i + j;
-#pragma unroll
-                for (int l = 0; l < 3; ++l) {
-                    const double w = wt[l * AD + m] * s3[l * AD + m] * Sg[i];
-                    cr[l] += w * (double)y.x;
-                    ci[l] += w * (double)y.y;
-                }
-            }
-#pragma unroll
-            for (int l = 0; l < 3; ++l) {
-                const double xr = wave_sum(cr[l]), xi = wave_sum(ci[l]);
-                e[l] += Sg[j] * Sg[j] * (xr * xr + xi * xi);
-            }
-        }
-#pragma unroll
-        for (int l = 0; l < 3; ++l) {
-            // each wave holds its rows' total in every lane; add waves in order
-            __syncthreads();
-            if (lane == 0) red[wave] = e[l];
-            __syncthreads();
-            double s = 0.0;
-            for (int q = 0; q < THREADS / 64; ++q) s += red[q];
-            res[l][0] = h * h * h * s;
-        }
-    }
-    // F: columns, one thread per column
-    if (em & 0x222) {
-        double f[3] = {0.0, 0.0, 0.0};
-        for (int i = tid; i < N; i += THREADS) {
-            double cr[3] = {0, 0, 0}, ci[3] = {0, 0, 0};
-            for (int j = 0; j < N; ++j) {
-                const V2 y = Y[(size_t)j * N + i];
-                const int m = i + j;
-#pragma unroll
-                for (int l = 0; l < 3; ++l) {
-                    const double w = wt[l * AD + m] * s3[l * AD + m] * Sg[j];
-                    cr[l] += w * (double)y.x;
-                    ci[l] += w * (double)y.y;
-                }
-            }
-#pragma unroll
-            for (int l = 0; l < 3; ++l) f[l] += Sg[i] * Sg[i] * (cr[l] * cr[l] + ci[l] * ci[l]);
-        }
-#pragma unroll
-        for (int l = 0; l < 3; ++l) res[l][1] = h * h * h * block_sum(f[l], red);
-    }
-    // G: anti-diagonals, one thread per anti-diagonal
-    if (em & 0x444) {
-        double g[3] = {0.0, 0.0, 0.0};
-        for (int m = tid; m < AD; m += THREADS) {
-            double cr = 0.0, ci = 0.0;
-            const int i0 = m - (N - 1) > 0 ? m - (N - 1) : 0, i1 = m < N - 1 ? m : N - 1;
-            for (int i = i0; i <= i1; ++i) {
-                const V2 y = Y[(size_t)(m - i) * N + i];
-                const double w = Sg[i] * Sg[m - i];
-                cr += w * (double)y.x;
-                ci += w * (double)y.y;
-            }
-#pragma unroll
-            for (int l = 0; l < 3; ++l) {
-                const double w3 = s3[l * AD + m];
-                g[l] += wt[l * AD + m] * w3 * w3 * (cr * cr + ci * ci);
-            }
-        }
-#pragma unroll
-        for (int l = 0; l < 3; ++l) res[l][2] = h * h * h * block_sum(g[l], red);
-    }
-    // H: full sum
-    if (em & 0x888) {
-        double cr[3] = {0, 0, 0}, ci[3] = {0, 0, 0};
-        for (int p = tid; p < N * N; p += THREADS) {
-            const int i = p % N, j = p / N, m = i + j;
-            const V2 y = Y[p];
-            const double s12 = Sg[i] * Sg[j];
-#pragma unroll
-            for (int l = 0; l < 3; ++l) {
-                const double w = wt[l * AD + m] * s3[l * AD + m] * s12;
-                cr[l] += w * (double)y.x;
-                ci[l] += w * (double)y.y;
-            }
-        }
-#pragma unroll
-        for (int l = 0; l < 3; ++l) {
-            const double xr = block_sum(cr[l], red), xi = block_sum(ci[l], red);
-            res[l][3] = h * h * h * h * (xr * xr + xi * xi);
-        }
-    }
-    if (tid == 0) {
-        double* o = a.partE + (size_t)it.d_index * 12;
-#pragma unroll
-        for (int l = 0; l < 3; ++l)
-#pragma unroll
-            for (int t = 0; t < 4; ++t) o[l * 4 + t] = ((em >> (4 * l + t)) & 1) ? res[l][t] : 0.0;
-    }
 }
 
 // Per CUT: sigma^2 = sum_f w_f sum_islands P1 P2 P3 [c_D R^3 D + Phi c_E R^2 E + ...],
@@ -826,16 +852,6 @@ int region_blocks_per_cu(bool fp32, int mu_method)
         e = mu_method == 0 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, region_queue_kernel<double, 0>, THREADS, 0)
                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, region_queue_kernel<double, 1>, THREADS, 0);
     return (e == hipSuccess && n > 0) ? n : 1;
-}
-
-hipError_t launch_egn(const EgnArgs& a, int n_delta, bool fp32, hipStream_t st)
-{
-    if (n_delta == 0) return hipSuccess;
-    if (fp32)
-        hipLaunchKernelGGL(egn_kernel<float>, dim3(n_delta), dim3(THREADS), 0, st, a);
-    else
-        hipLaunchKernelGGL(egn_kernel<double>, dim3(n_delta), dim3(THREADS), 0, st, a);
-    return hipGetLastError();
 }
 
 hipError_t launch_assemble(const AssembleArgs& a, hipStream_t st)
