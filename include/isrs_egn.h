@@ -165,6 +165,24 @@ int32_t isrs_eval_eta(isrs_ctx* ctx, const isrs_numerics* numerics, const int32_
 int32_t isrs_eval_eta_dev(isrs_ctx* ctx, const isrs_numerics* numerics, const int32_t* cuts, int32_t n_cut,
                           double* eta_dev, double* sigma2_dev, double* terms_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * evaluation and outputs as isrs_eval_eta_dev, with every device buffer
+ * beyond the caller's inputs and outputs (tables, work list, partial sums,
+ * coherent-sum accumulators, queue counter) placed in a fixed 64 MiB device
+ * array that each GPU holds from library load to process exit.  The call
+ * makes no hipMalloc, hipFree or hipHostMalloc; it plans on the host and
+ * copies the tables from host memory into that array on the context's stream.
+ * Plans with coherent sums get as many persistent blocks as accumulator slots
+ * fit after the tables (at least one).  An evaluation whose buffers exceed
+ * the 64 MiB fails with ISRS_E_ARG, naming the size it needs; nothing is
+ * launched.  Every context on a GPU shares that GPU's array, which keeps the
+ * last call's contents: calls that overlap on one GPU (two contexts on
+ * different streams) race, so order them.  The surrogate, per-CUT steps and
+ * explicit squares are not offered here. */
+int32_t isrs_eval_eta_dev_noalloc(isrs_ctx* ctx, const isrs_numerics* numerics, const int32_t* cuts,
+                                  int32_t n_cut, double* eta_dev, double* sigma2_dev, double* terms_dev);
+
 /* eta with a sampling step per CUT: dz_km[q] replaces numerics->dz_km for
  * cuts[q] (Sec. III-C: the segment form's step can follow the COI's
  * frequency).  CUTs sharing a step share segment tables.  Outputs, units and

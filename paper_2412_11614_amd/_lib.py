@@ -40,6 +40,7 @@ EXPORTED = [
     "isrs_surrogate_num_params", "isrs_surrogate_get_params", "isrs_surrogate_set_params",
     "isrs_surrogate_grad", "isrs_surrogate_save", "isrs_surrogate_load", "isrs_surrogate_get_target_scale",
     "isrs_eval_eta_surrogate", "isrs_eval_eta_dz", "isrs_choose_dz", "isrs_surrogate_datagen_batch",
+    "isrs_eval_eta_dev_noalloc",
 ]
 
 SUR_FEATURES = 16
@@ -115,6 +116,7 @@ def lib():
     L.isrs_set_ptot_override.argtypes = [vp, C.c_double]
     L.isrs_eval_eta.argtypes = [vp, C.POINTER(Numerics_c), ip, C.c_int32, dp, dp, dp]
     L.isrs_eval_eta_dev.argtypes = [vp, C.POINTER(Numerics_c), ip, C.c_int32, vp, vp, vp]
+    L.isrs_eval_eta_dev_noalloc.argtypes = [vp, C.POINTER(Numerics_c), ip, C.c_int32, vp, vp, vp]
     L.isrs_eval_psd.argtypes = [vp, C.POINTER(Numerics_c), ip, C.c_int32, dp, dp]
     L.isrs_eval_islands.argtypes = [vp, C.POINTER(Numerics_c), C.c_int32, ip, C.c_int32, dp]
     L.isrs_set_profiling.argtypes = [vp, C.c_int32]
@@ -521,8 +523,9 @@ class Engine:
                                            float(target_db), _dp(dz), _dp(err)))
         return dz, err
 
-    def eval_eta_dev(self, numerics, cuts, eta_dev, sigma2_dev=None, terms_dev=None, **override):
-        """Device outputs (torch tensors of float64 on the context's GPU); stream-ordered."""
+    def eval_eta_dev(self, numerics, cuts, eta_dev, sigma2_dev=None, terms_dev=None, noalloc=False, **override):
+        """Device outputs (torch tensors of float64 on the context's GPU); stream-ordered.
+        noalloc=True calls isrs_eval_eta_dev_noalloc (device scratch from the library's fixed array)."""
         nu = numerics if isinstance(numerics, Numerics_c) else numerics_struct(numerics, **override)
         cuts = np.ascontiguousarray(np.asarray(cuts, dtype=np.int32))
         ptr = lambda t: None if t is None else C.c_void_p(t.data_ptr())
@@ -535,8 +538,8 @@ class Engine:
             raise ValueError("sigma2_dev too small")
         if terms_dev is not None and terms_dev.numel() < 5 * len(cuts):
             raise ValueError("terms_dev too small")
-        self._check(self._L.isrs_eval_eta_dev(self._h, C.byref(nu), _ip(cuts), len(cuts), ptr(eta_dev),
-                                              ptr(sigma2_dev), ptr(terms_dev)))
+        fn = self._L.isrs_eval_eta_dev_noalloc if noalloc else self._L.isrs_eval_eta_dev
+        self._check(fn(self._h, C.byref(nu), _ip(cuts), len(cuts), ptr(eta_dev), ptr(sigma2_dev), ptr(terms_dev)))
 
     def eval_psd(self, numerics, cuts, **override):
         nu = numerics if isinstance(numerics, Numerics_c) else numerics_struct(numerics, **override)

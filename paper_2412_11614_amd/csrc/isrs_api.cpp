@@ -177,6 +177,13 @@ struct isrs_ctx {
     int n_cu = 0;
 
     Workspace* ws = nullptr;
+
+    // allocation-free evaluation: this device's scratch array, the host plan
+    // of the last such call (its tables may still be on their way to the
+    // device) and an event after its uploads
+    void* scratch = nullptr;
+    Plan* scratch_plan = nullptr;
+    hipEvent_t ev_scratch = nullptr;
 };
 
 namespace {
@@ -689,6 +696,80 @@ int32_t plan_upload(isrs_ctx* c, Workspace& w, const Plan& p, hipStream_t st)
     return ISRS_OK;
 }
 
+// Device side of a plan carved out of the allocation-free scratch: the
+// buffers of plan_upload at fixed offsets, filled by copies from the plan's
+// own host vectors, with nothing allocated.  A plan with coherent sums gets as
+// many persistent blocks (one accumulator slot each) as fit after its tables.
+int32_t plan_upload_scratch(isrs_ctx* c, Workspace& w, Plan& p, char* base, size_t bytes, hipStream_t st)
+{
+    size_t off = 0;
+    auto carve = [&](DevBuf& d, size_t n) {
+        d.p = base + off;
+        d.cap = n;
+        off += (n + 255) & ~size_t(255);
+    };
+    auto nb = [](const auto& v) { return v.size() * sizeof(v[0]); };
+    carve(w.links, nb(p.links));
+    carve(w.spans, nb(p.spans));
+    carve(w.seg, p.fp32 ? nb(p.seg32) : nb(p.seg64));
+    carve(w.Sg, nb(p.Sg));
+    carve(w.wt, nb(p.wt));
+    carve(w.s3, nb(p.s3));
+    carve(w.livep, nb(p.livep));
+    carve(w.runs, nb(p.runs));
+    carve(w.adrun, nb(p.adrun));
+    carve(w.insts, nb(p.insts));
+    carve(w.items, nb(p.items));
+    carve(w.order, nb(p.order));
+    carve(w.power, nb(p.power));
+    carve(w.phi, nb(p.phi));
+    carve(w.psi, nb(p.psi));
+    carve(w.partD, std::max<size_t>(1, p.items.size()) * p.n_groups * 3 * sizeof(double));
+    carve(w.partE, std::max<size_t>(1, p.dlist.size()) * 12 * sizeof(double));
+    carve(w.counter, sizeof(int) * std::max<size_t>(1, p.chunk_begin.size()));
+    const size_t slot = eslot(p.N) * sizeof(double2);
+    if (!p.dlist.empty()) {
+        const size_t fit = off < bytes ? (bytes - off) / slot : 0;
+        if (fit >= 1) {
+            p.queue_blocks = (int)std::min<size_t>((size_t)p.queue_blocks, fit);
+            carve(w.eacc, (size_t)p.queue_blocks * slot);
+        } else {
+            off += slot;
+        }
+    }
+    if (off > bytes)
+        return fail(c, ISRS_E_ARG, "the evaluation needs " + std::to_string(off) +
+                                       " bytes of device scratch; the allocation-free entry point has " +
+                                       std::to_string(bytes));
+    const std::string bad = plan_check(p);
+    if (!bad.empty()) return fail(c, ISRS_E_ARG, "internal plan check: " + bad);
+    auto put = [&](DevBuf& d, const void* src, size_t n) -> int32_t {
+        if (n) HIP_TRY(c, hipMemcpyAsync(d.p, src, n, hipMemcpyHostToDevice, st));
+        return ISRS_OK;
+    };
+    int32_t rc;
+    if ((rc = put(w.links, p.links.data(), nb(p.links)))) return rc;
+    if ((rc = put(w.spans, p.spans.data(), nb(p.spans)))) return rc;
+    if (p.fp32) {
+        if ((rc = put(w.seg, p.seg32.data(), nb(p.seg32)))) return rc;
+    } else {
+        if ((rc = put(w.seg, p.seg64.data(), nb(p.seg64)))) return rc;
+    }
+    if ((rc = put(w.Sg, p.Sg.data(), nb(p.Sg)))) return rc;
+    if ((rc = put(w.wt, p.wt.data(), nb(p.wt)))) return rc;
+    if ((rc = put(w.s3, p.s3.data(), nb(p.s3)))) return rc;
+    if ((rc = put(w.livep, p.livep.data(), nb(p.livep)))) return rc;
+    if ((rc = put(w.runs, p.runs.data(), nb(p.runs)))) return rc;
+    if ((rc = put(w.adrun, p.adrun.data(), nb(p.adrun)))) return rc;
+    if ((rc = put(w.insts, p.insts.data(), nb(p.insts)))) return rc;
+    if ((rc = put(w.items, p.items.data(), nb(p.items)))) return rc;
+    if ((rc = put(w.order, p.order.data(), nb(p.order)))) return rc;
+    if ((rc = put(w.power, p.power.data(), nb(p.power)))) return rc;
+    if ((rc = put(w.phi, p.phi.data(), nb(p.phi)))) return rc;
+    if ((rc = put(w.psi, p.psi.data(), nb(p.psi)))) return rc;
+    return ISRS_OK;
+}
+
 hipEvent_t pool_event(Workspace& w, size_t i)
 {
     while (w.ev_pool.size() <= i) {
@@ -851,7 +932,7 @@ LinkInput ctx_link(const isrs_ctx* c, const int32_t* cuts, int n_cut)
 int32_t evaluate(isrs_ctx* c, const isrs_numerics* nu, const int32_t* cuts, int n_cut, const int32_t* kappa12,
                  int m_explicit, double* eta_d, double* s2_d, double* terms_d, double* psd_d,
                  double* partials_host, SurrogateFill* sf = nullptr, const double* dz_per_cut = nullptr,
-                 std::vector<int>* plan_order = nullptr)
+                 std::vector<int>* plan_order = nullptr, bool noalloc = false)
 {
     auto t0 = std::chrono::steady_clock::now();
     if (!c) return ISRS_E_ARG;
@@ -923,8 +1004,24 @@ int32_t evaluate(isrs_ctx* c, const isrs_numerics* nu, const int32_t* cuts, int 
     } catch (const std::bad_alloc&) {
         return fail(c, ISRS_E_NOMEM, "host allocation failed");
     }
-    Workspace& w = *c->ws;
     int32_t rc;
+    if (noalloc) {
+        // the device buffers are views into the scratch array; the plan's host
+        // vectors stay with the context until the uploads are done
+        if (!c->scratch || !c->ev_scratch || sf || partials_host || psd_d)
+            return fail(c, ISRS_E_STATE, "allocation-free evaluation unavailable");
+        HIP_TRY(c, hipEventSynchronize(c->ev_scratch));
+        Workspace view;
+        if ((rc = plan_upload_scratch(c, view, p, static_cast<char*>(c->scratch), NOALLOC_BYTES, c->stream)))
+            return rc;
+        HIP_TRY(c, hipEventRecord(c->ev_scratch, c->stream));
+        auto t1 = std::chrono::steady_clock::now();
+        if ((rc = plan_enqueue(c, view, p, c->stream, eta_d, s2_d, terms_d, nullptr, true, nullptr))) return rc;
+        record_stats(c, p, std::chrono::duration<double, std::milli>(t1 - t0).count(), false);
+        std::swap(*c->scratch_plan, p);
+        return ISRS_OK;
+    }
+    Workspace& w = *c->ws;
     if ((rc = plan_upload(c, w, p, c->stream))) return rc;
     if (sf) HIP_TRY(c, w.sur.ensure((size_t)max_items * p.N * p.N * p.links[0].n_sp * sizeof(float)));
     auto t1 = std::chrono::steady_clock::now();
@@ -1278,10 +1375,23 @@ int32_t isrs_create(isrs_ctx** out, int32_t device, void* hip_stream)
             g_create_error = "hipSetDevice failed";
             return ISRS_E_DEVICE;
         }
+        // this device's copy of the allocation-free scratch, looked up once per device
+        c->scratch_plan = new (std::nothrow) Plan();
+        if (!c->scratch_plan || noalloc_scratch(device, &c->scratch) != hipSuccess ||
+            hipEventCreateWithFlags(&c->ev_scratch, hipEventDisableTiming) != hipSuccess) {
+            if (c->ev_scratch) (void)hipEventDestroy(c->ev_scratch);
+            delete c->scratch_plan;
+            delete w;
+            delete c;
+            g_create_error = "device scratch lookup failed";
+            return ISRS_E_DEVICE;
+        }
         if (hip_stream) {
             c->stream = reinterpret_cast<hipStream_t>(hip_stream);
         } else {
             if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+                (void)hipEventDestroy(c->ev_scratch);
+                delete c->scratch_plan;
                 delete w;
                 delete c;
                 g_create_error = "stream creation failed";
@@ -1304,6 +1414,8 @@ int32_t isrs_destroy(isrs_ctx* c)
         (void)hipStreamSynchronize(c->stream);
         c->ws->release();
         delete c->ws;
+        delete c->scratch_plan;
+        if (c->ev_scratch) (void)hipEventDestroy(c->ev_scratch);
         if (c->own_stream) (void)hipStreamDestroy(c->stream);
         delete c;
         return ISRS_OK;
@@ -1399,6 +1511,19 @@ int32_t isrs_eval_eta_dev(isrs_ctx* c, const isrs_numerics* nu, const int32_t* c
         if (!c) return ISRS_E_ARG;
         if (!eta_dev) return fail(c, ISRS_E_ARG, "eta output is null");
         return evaluate(c, nu, cuts, n_cut, nullptr, 0, eta_dev, sigma2_dev, terms_dev, nullptr, nullptr);
+    } catch (...) {
+        return abi_exception(c);
+    }
+}
+
+int32_t isrs_eval_eta_dev_noalloc(isrs_ctx* c, const isrs_numerics* nu, const int32_t* cuts, int32_t n_cut,
+                                  double* eta_dev, double* sigma2_dev, double* terms_dev)
+{
+    try {
+        if (!c) return ISRS_E_ARG;
+        if (!eta_dev) return fail(c, ISRS_E_ARG, "eta output is null");
+        return evaluate(c, nu, cuts, n_cut, nullptr, 0, eta_dev, sigma2_dev, terms_dev, nullptr, nullptr, nullptr,
+                        nullptr, nullptr, true);
     } catch (...) {
         return abi_exception(c);
     }

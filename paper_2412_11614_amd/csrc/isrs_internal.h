@@ -159,6 +159,13 @@ struct AssembleArgs {
     int n_cut;
 };
 
+// Device scratch of the allocation-free evaluation (isrs_eval_eta_dev_noalloc):
+// a file-scope array in isrs_kernels.hip, one copy per GPU, held until the
+// process ends.  noalloc_scratch() returns this device's copy (the device must
+// be current); the address is looked up once per device and kept.
+constexpr size_t NOALLOC_BYTES = size_t(64) << 20;
+hipError_t noalloc_scratch(int device, void** ptr);
+
 // Kernel launchers (isrs_kernels.hip).  blocks = 0 launches one block per
 // unit; blocks > 0 launches that many persistent blocks on the queue.
 hipError_t launch_region(const RegionArgs& a, int blocks, bool fp32, hipStream_t st);

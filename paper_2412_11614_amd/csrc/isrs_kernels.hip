@@ -23,7 +23,37 @@
 // [-1/2, 1/2] before the sine / cosine.
 #include "isrs_internal.h"
 
+#include <mutex>
+
 namespace isrs {
+
+// Scratch of the allocation-free evaluation.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in for the symbol):
+// it passes the device address that hipGetSymbolAddress returns for the
+// current device.
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+hipError_t noalloc_scratch(int device, void** ptr)
+{
+    *ptr = nullptr;
+    if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = p;
+    }
+    *ptr = g_scratch_ptr[device];
+    return hipSuccess;
+}
 
 namespace {
 
