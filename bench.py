@@ -1,18 +1,25 @@
 """Throughput of the ISRS-EGN hot path on one MI355X.
 
 One step = one pass of the whole hot path (segment tables, island work list,
-region kernel over every folded channel-pair square, coherent EGN sums,
-per-CUT assembly) for every CUT of the C+L workload: 100 x 96 GBd channels on
-a 100 GHz grid (10 THz), 10 spans of 80-100 km, 256 x 256 grid per square,
-FP32 integrand with FP64 phases and sums.  Inputs are resident on the GPU
-when the timed region starts; outputs stay on the GPU.
+the region kernel over every folded channel-pair square with the coherent
+E/F/G/H sums on its tile, the per-CUT assembly of Eq. 15 and eta of Eq. 11)
+for one CUT of the S+C+L workload: 150 x 100 GBd channels on a 100 GHz grid
+(15 THz), 24 dBm, 40 spans of 80 km with per-span fibre draws, 1024 x 1024
+grid per square, everything in FP64.  The timed steps take CUTs spread evenly
+over the band (step i: CUT round((i + 1/2) 150 / K - 1/2)); the whole band is
+150 such steps, so CUT/s of the sample is the rate of the 150-CUT job.
+Inputs are resident on the GPU when the timed region starts; outputs stay on
+the GPU.
 
 Prints one JSON line.  The CPU-baseline leg times the FP64 oracle (integral
-form of the z-integral) on a bounded sample of the same workload.
+form of the z-integral) on a bounded sample of the same workload; the
+accuracy block compares GPU results with stored oracle values
+(tests/golden/, written by scripts that call only the oracle).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -23,36 +30,64 @@ sys.path.insert(0, ROOT)
 
 import numpy as np  # noqa: E402
 
-# The region kernel is bound by FP32 vector ALU issue.  Peak: the chip's FP32
-# vector rate, 256 CU x 4 SIMD x 16 lanes x 2 FLOP (FMA) x 2 x 2.4 GHz =
-# 157.3 TFLOP/s.  gfx950 issues non-packed v_fma_f32 at up to ~1.9 wave
-# instructions per CU per clock (149 TFLOP/s measured on independent chains),
-# so this is also the ceiling for a build without packed FP32.
-PEAK_FP32_TFLOPS = 256 * 4 * 16 * 2 * 2 * 2.4e9 / 1e12
+# Vector ALU peaks of the chip: 256 CU x 4 SIMD x 16 lanes x 2 FLOP (FMA) x 2.4 GHz
+# = 78.6 TFLOP/s in FP64, twice that (157.3) in FP32.  gfx950 issues non-packed
+# v_fma_f32 at up to ~1.9 wave-instructions per CU per clock (149 TFLOP/s measured
+# on independent chains), so 157.3 is also the ceiling of a build without packed
+# FP32.
+PEAK_FP64_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+PEAK_FP32_TFLOPS = 2 * PEAK_FP64_TFLOPS
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+PROFILES = os.path.join(ROOT, "profiles")
+HEADLINE_PROFILE = "region_queue_kernel_fp64_scl150ch_40span_1024"
+CL_PROFILE = "region_queue_kernel_fp32_cl100ch_10span_256"
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "region_kernel_traffic_cl100ch_10span_256.md")
-
-
-def measured_traffic():
-    """HBM bytes per region launch from the committed counter summary, or None
-    when the kernel source has changed since the counters were taken."""
-    import hashlib
-
-    try:
-        text = open(TRAFFIC_FILE).read()
-    except OSError:
-        return None
-    fields = dict(line.split(": ", 1) for line in text.splitlines()
-                  if line.startswith(("traffic_bytes_per_launch: ", "kernel_source_sha256: ")))
-    csrc = os.path.join(ROOT, "paper_2412_11614_amd", "csrc")
+def kernel_source_hash():
     h = hashlib.sha256()
     for name in ("isrs_kernels.hip", "isrs_internal.h"):
-        with open(os.path.join(csrc, name), "rb") as f:
+        with open(os.path.join(ROOT, "paper_2412_11614_amd", "csrc", name), "rb") as f:
             h.update(f.read())
-    if fields.get("kernel_source_sha256", "").strip() != h.hexdigest():
-        return None
-    return float(fields["traffic_bytes_per_launch"])
+    return h.hexdigest()
+
+
+def profile_fields(stem):
+    """key: value lines of a committed counter summary, or {} when the kernel
+    source has changed since the counters were taken."""
+    out = {}
+    for kind in ("traffic", "counters"):
+        try:
+            text = open(os.path.join(PROFILES, f"{stem}_{kind}.md")).read()
+        except OSError:
+            continue
+        fields = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line and
+                      line.split(": ", 1)[0].replace("_", "").isalnum() and not line.startswith(("|", "*", "#")))
+        if fields.get("kernel_source_sha256", "").strip() != kernel_source_hash():
+            continue
+        out.update({k: v.strip() for k, v in fields.items()})
+    return out
+
+
+def kernel_roofline(st, peak, name, stem):
+    """Roofline of one region launch from the library's counters and HIP-event
+    time: algorithmic FLOP of the segment method as evaluated, 4 K_s + 30 per
+    live (point, span) (two FMAs per segment of the real-coefficient sum, plus
+    the per-point setup: q, I_0, the rotation e^{i Theta}, the accumulation)."""
+    per_launch_ms = st.region_ms / max(1, st.region_launches)
+    point_spans = (st.alg_flop - 8.0 * st.horner_steps) / 30.0
+    flop = (4.0 * st.horner_steps + 30.0 * point_spans) / max(1, st.region_launches)
+    achieved = flop / (per_launch_ms * 1e-3) / 1e12
+    prof = profile_fields(stem)
+    traffic = float(prof["traffic_bytes_per_launch"]) if "traffic_bytes_per_launch" in prof else None
+    r = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+         "traffic": traffic, "kernel": name, "per_launch_ms": per_launch_ms, "flop_per_launch": flop,
+         "flop_per_unit": "4 K_s + 30 per live (point, span)",
+         # the complex-Horner count (8 K_s + 30) prices each segment at twice what the
+         # real-coefficient recurrence needs; as a fraction it can pass 1
+         "frac_complex_horner_count": st.alg_flop / max(1, st.region_launches) / (per_launch_ms * 1e-3) / 1e12 / peak}
+    if "fma_flop_per_s_frac" in prof:
+        r["frac_counter"] = float(prof["fma_flop_per_s_frac"])
+    return r
 
 
 def log(*a):
@@ -62,7 +97,8 @@ def log(*a):
 def cpu_baseline(wl, n_squares, seed=0):
     """Times the oracle (integral-form FWM factor, FP64) on n_squares randomly
     drawn live channel-pair squares of the middle CUT at the full grid, using
-    all host cores (one square per thread), and scales to CUTs per second."""
+    all host cores (one square per thread), and scales to CUTs per second by
+    the CUT's number of live squares (unfolded, as the oracle evaluates them)."""
     import concurrent.futures as cf
 
     import oracle
@@ -86,6 +122,7 @@ def cpu_baseline(wl, n_squares, seed=0):
         cores = len(os.sched_getaffinity(0))
     except AttributeError:
         pass
+    n_squares = n_squares or cores
     threads = max(1, min(cores, n_squares))
     t0 = time.perf_counter()
     with cf.ThreadPoolExecutor(threads) as ex:
@@ -94,31 +131,52 @@ def cpu_baseline(wl, n_squares, seed=0):
     cut_seconds = wall / n_squares * len(live)
     return {"value": 1.0 / cut_seconds, "unit": "CUT/s", "cores": threads, "kind": "oracle",
             "sample": (f"{n_squares} random live squares of CUT {cut} (of {len(live)}) at the full "
-                       f"{wl.numerics.n_grid}x{wl.numerics.n_grid} grid, 10 spans, integral-form mu; "
-                       f"{wall:.1f} s wall on {threads} threads, scaled by squares per CUT")}
+                       f"{wl.numerics.n_grid}x{wl.numerics.n_grid} grid, {len(wl.link.spans)} spans, "
+                       f"integral-form mu; {wall:.1f} s wall on {threads} threads, scaled by squares per CUT")}
 
 
-def batched_leg(eng, n_links, n_plain, W, torch):
-    """Uneven-link workload in one queue launch per chunk, replayed from a
-    captured graph, against the plain one-link-at-a-time path."""
+def batched_leg(eng, n_links, n_plain, W, torch, tune_links=64):
+    """Uneven-link workload in one persistent queue launch, replayed from a
+    captured graph, with the launch shape from the project's autotuner (tuned
+    on the batch's first tune_links links, whose shape key the full batch
+    shares, through the tuning cache), against the default shape and the plain
+    one-link-at-a-time path."""
+    import tempfile
+
     links = W.batch_links(n_links=n_links)
     nu = links[0].numerics                       # 64 x 64, FP32 integrand / FP64 phase
+    cache = os.path.join(tempfile.mkdtemp(prefix="isrs_tune_"), "autotune.jsonl")
+    t0 = time.perf_counter()
+    bt = eng.batch(links[:min(tune_links, n_links)])
+    bt.autotune(nu, cache)
+    bt.close()
+    t_tune = time.perf_counter() - t0
     b = eng.batch(links)
     eta_b = torch.empty(b.n_cuts, dtype=torch.float64, device="cuda")
-    log(f"batched: {n_links} links, {b.n_cuts} CUTs: warm-up (plan + eager run), capture")
-    eng.set_profiling(True)                      # the eager first call also reports the work done
-    t0 = time.perf_counter()
-    b.eval_dev(nu, eta_b)
-    torch.cuda.synchronize()
-    t_first = time.perf_counter() - t0
-    st = eng.stats()
-    eng.set_profiling(False)
-    b.eval_dev(nu, eta_b)                        # capture the graph
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    b.eval_dev(nu, eta_b)                        # timed replay
-    torch.cuda.synchronize()
-    t_batch = time.perf_counter() - t0
+
+    def timed_replay():
+        eng.set_profiling(True)                  # the eager first call reports the work done
+        t0 = time.perf_counter()
+        b.eval_dev(nu, eta_b)
+        torch.cuda.synchronize()
+        t_first = time.perf_counter() - t0
+        st = eng.stats()
+        eng.set_profiling(False)
+        b.eval_dev(nu, eta_b)                    # capture the graph
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.eval_dev(nu, eta_b)                    # timed replay
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, t_first, st
+
+    log(f"batched: {n_links} links, {b.n_cuts} CUTs, default launch shape")
+    t_default, t_first, st_default = timed_replay()
+    shape_default = b.tuning()
+    eta_default = eta_b.cpu().numpy().copy()
+    b.autotune(nu, cache)                        # cache hit: re-plans with the tuned shape
+    log(f"batched: tuned shape {b.tuning()}")
+    t_batch, _, st = timed_replay()
+    shape_tuned = b.tuning()
     eta_batch = eta_b.cpu().numpy()
     # plain path on the first n_plain links, same numerics
     n_plain = min(n_plain, n_links)
@@ -140,17 +198,27 @@ def batched_leg(eng, n_links, n_plain, W, torch):
         ref = eta_plain[:len(w.cuts)].cpu().numpy()
         agree = max(agree, float(np.max(np.abs(10 * np.log10(eta_batch[off[i]:off[i + 1]] / ref)))))
     b.close()
+    per_launch_s = st.region_ms * 1e-3 / max(1, st.region_launches)
+    point_spans = (st.alg_flop - 8.0 * st.horner_steps) / 30.0
+    flop = 4.0 * st.horner_steps + 30.0 * point_spans
     return {"workload": (f"{n_links} links: 20-100 active of 100 x 96 GBd / 100 GHz slots, P U[-3,3] dBm, "
                          f"1-30 spans U[50,120] km, alpha and Cr per link (seed 3), 64x64 per square, "
                          f"all active channels under test"),
             "n_cut": int(b.n_cuts), "value": b.n_cuts / t_batch, "unit": "CUT/s",
             "ms_per_step": 1e3 * t_batch, "first_call_s": t_first,
+            "tuned_shape": shape_tuned, "default_shape": shape_default, "default_ms_per_step": 1e3 * t_default,
+            "tuning_s": t_tune, "tuned_on_links": min(tune_links, n_links),
+            "max_abs_db_tuned_vs_default": float(np.max(np.abs(10 * np.log10(eta_batch / eta_default)))),
+            "region_launches": st.region_launches,
             "plain_path": {"links": n_plain, "n_cut": cuts_plain, "value": cuts_plain / t_plain, "unit": "CUT/s"},
             "speedup_vs_plain": (b.n_cuts / t_batch) / (cuts_plain / t_plain),
             "max_abs_db_batch_vs_plain": agree,
-            # algorithmic FLOP of the step (8 K + 30 per live point-span) over the replay's wall time
-            "alg_tflops": st.alg_flop / t_batch / 1e12, "frac": st.alg_flop / t_batch / 1e12 / PEAK_FP32_TFLOPS,
-            "region_ms_eager": st.region_ms, "live_points": st.n_points_live}
+            # FLOP of the segment method as evaluated (4 K + 30 per live point-span) per region
+            # launch over its HIP-event time, against the FP32 vector peak
+            "tflops": flop / max(1, st.region_launches) / per_launch_s / 1e12,
+            "frac": flop / max(1, st.region_launches) / per_launch_s / 1e12 / PEAK_FP32_TFLOPS,
+            "region_ms_eager": st.region_ms, "live_points": st.n_points_live,
+            "default_region_ms_eager": st_default.region_ms}
 
 
 def integral_form_leg(eng, wl, W, torch, n_cuts=10):
@@ -394,17 +462,116 @@ def surrogate_link_leg(eng, torch, W, train_rows, members, wl, cuts, ref, n_link
             "train_loss_ln2": [float(v) for v in loss], "held_out_8192": held, "eta_in_the_loop": loop}
 
 
+def _gold(stage):
+    path = os.path.join(GOLDEN, f"oracle_percut_{stage}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)
+
+
+def headline_accuracy(eng, W):
+    """The headline path (FP64, segment form) on the S+C+L workload against
+    stored oracle values of the model (integral form, adaptive quadrature):
+    per-CUT eta at 64 x 64 (8 seeded CUTs) and 128 x 128 (CUTs 0, 75), and the
+    GN sums of every near-CUT square of four CUTs at the full 1024 x 1024 grid
+    (an oracle CUT at that grid is out of reach; the near squares carry most of
+    its eta)."""
+    out = {}
+    errs = []
+    for stage, n in (("scl64", 64), ("scl128", 128)):
+        g = _gold(stage)
+        if g is None:
+            continue
+        wl = W.sclband_150ch_40span(n_grid=n)
+        eng.load(wl)
+        got = eng.eval_eta(wl.numerics, g["cuts"], precision=W.PREC_FP64, n=n)["eta"]
+        e = np.abs(10 * np.log10(got / np.array(g["eta"])))
+        out[f"eta_{n}x{n}"] = {"cuts": g["cuts"], "max_abs_db": float(e.max())}
+        errs.append(e.max())
+    g = _gold("scl1024sq")
+    if g is not None:
+        wl = W.sclband_150ch_40span(n_grid=1024)
+        eng.load(wl)
+        by_cut = {}
+        for e in g["squares"]:
+            by_cut.setdefault(e["cut"], []).append(e)
+        worst = 0.0
+        for cut, ents in sorted(by_cut.items()):
+            keys = [(e["k1"], e["k2"]) for e in ents]
+            ref = np.array([e["terms"] for e in ents])
+            got = eng.eval_islands(wl.numerics, cut, keys, precision=W.PREC_FP64)
+            worst = max(worst, abs(10 * np.log10(got[:, :, 0].sum() / ref[:, :, 0].sum())))
+        out["near_cut_squares_1024"] = {"cuts": sorted(by_cut), "squares": len(g["squares"]),
+                                        "max_abs_db_of_gn_sum": float(worst)}
+        errs.append(worst)
+    out["max_abs_db_vs_oracle"] = float(max(errs)) if errs else None
+    out["within_0p01_db"] = bool(errs) and max(errs) <= 0.01
+    return out
+
+
+def cl_leg(eng, W, torch, reps=2):
+    """The C+L workload (100 x 96 GBd, 10 spans, 256 x 256 per square): all 100
+    CUTs per step in the FP32-integrand / FP64-phase variant and in FP64, with
+    both against stored oracle values (8 CUTs at 256 x 256, all CUTs at 64 x 64)."""
+    wl = W.cl_100ch_10span(n_grid=256)
+    cuts = wl.cuts
+    n = len(cuts)
+    eng.load(wl)
+    eta = torch.empty(n, dtype=torch.float64, device="cuda")
+    res = {"workload": ("C+L 10 THz: 100 x 96 GBd on 100 GHz, roll-off 0.04, 20 dBm with +-2 dB tilt, 10 spans "
+                        "U[80,100] km (seed 2), 16QAM/64QAM alternating, EGN on, 256x256 per square, all 100 CUTs")}
+    out_eta = {}
+    for name, prec, k in (("fp32_phase64", W.PREC_FP32_PHASE64, reps), ("fp64", W.PREC_FP64, 1)):
+        eng.eval_eta_dev(wl.numerics, cuts[:4], eta, precision=prec)        # warm (plan shapes, code)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            eng.eval_eta_dev(wl.numerics, cuts, eta, precision=prec)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / k
+        out_eta[prec] = eta.cpu().numpy().copy()
+        eng.set_profiling(True)
+        eng.eval_eta_dev(wl.numerics, cuts, eta, precision=prec)
+        torch.cuda.synchronize()
+        st = eng.stats()
+        eng.set_profiling(False)
+        fp32 = prec == W.PREC_FP32_PHASE64
+        res[name] = {"value": n / dt, "unit": "CUT/s", "ms_per_step": 1e3 * dt,
+                     "roofline": kernel_roofline(st, PEAK_FP32_TFLOPS if fp32 else PEAK_FP64_TFLOPS,
+                                                 "region_queue_kernel<%s, 0>" % ("float" if fp32 else "double"),
+                                                 CL_PROFILE if fp32 else "none"),
+                     "region_launches": st.region_launches, "squares": st.n_squares,
+                     "delta_squares": st.n_delta_squares}
+    acc = {"fp32_vs_fp64_max_abs_db": float(np.max(np.abs(10 * np.log10(out_eta[W.PREC_FP32_PHASE64] /
+                                                                          out_eta[W.PREC_FP64]))))}
+    g = _gold("cl256")
+    if g is not None:
+        pos = np.searchsorted(cuts, g["cuts"])
+        for prec, name in ((W.PREC_FP32_PHASE64, "fp32_phase64"), (W.PREC_FP64, "fp64")):
+            e = np.abs(10 * np.log10(out_eta[prec][pos] / np.array(g["eta"])))
+            acc[f"{name}_vs_oracle_256_max_abs_db"] = float(e.max())
+        acc["oracle_256_cuts"] = g["cuts"]
+    g = _gold("cl64")
+    if g is not None:
+        for prec, name in ((W.PREC_FP32_PHASE64, "fp32_phase64"), (W.PREC_FP64, "fp64")):
+            got = eng.eval_eta(wl.numerics, g["cuts"], precision=prec, n=64)["eta"]
+            acc[f"{name}_vs_oracle_64_all_cuts_max_abs_db"] = float(np.max(np.abs(10 * np.log10(got / np.array(g["eta"])))))
+    res["accuracy"] = acc
+    return res, wl, out_eta[W.PREC_FP32_PHASE64]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--grid", type=int, default=256)
-    ap.add_argument("--cpu-squares", type=int, default=400)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-squares", type=int, default=0,
+                    help="oracle squares of the CPU baseline (0: one per host thread)")
+    ap.add_argument("--only-headline", action="store_true", help="the timed steps only (for counter runs)")
     ap.add_argument("--mu-map", type=int, default=1, help="closed-form accuracy map leg (0 = skip)")
     ap.add_argument("--outer-nf", type=int, default=5, help="outer-integral leg samples (1 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--batch-links", type=int, default=512,
                     help="links of the batched leg (0 = skip)")
     ap.add_argument("--plain-links", type=int, default=48,
@@ -416,8 +583,6 @@ def main():
                     help="query points of the surrogate leg (0 = skip)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the steps, copy this many MiB device-to-device (counter calibration)")
-    ap.add_argument("--traffic-bytes", type=float, default=None,
-                    help="override the HBM bytes per region launch (default: the committed counter summary)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the path is single-GPU "
@@ -431,117 +596,106 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    wl = W.cl_100ch_10span(n_grid=args.grid, precision=W.PREC_FP32_PHASE64)
-    cuts = wl.cuts
-    n_cut = len(cuts)
+    wl = W.sclband_150ch_40span(n_grid=1024, precision=W.PREC_FP64)
+    n_ch = wl.spectrum.n_ch
+    K = args.steps
+    step_cuts = [int(round((i + 0.5) * n_ch / K - 0.5)) % n_ch for i in range(K)] if K <= n_ch \
+        else [i % n_ch for i in range(K)]
     stream = torch.cuda.Stream()          # shared with the library: torch and the kernels stay ordered
     torch.cuda.set_stream(stream)
     eng = _lib.Engine(0, stream=stream)
     eng.load(wl)
-    eta = torch.empty(n_cut, dtype=torch.float64, device=dev)
-    s2 = torch.empty(n_cut, dtype=torch.float64, device=dev)
-    terms = torch.empty(n_cut * 5, dtype=torch.float64, device=dev)
+    eta = torch.empty(max(K, 1), dtype=torch.float64, device=dev)
+    s2 = torch.empty(max(K, 1), dtype=torch.float64, device=dev)
+    terms = torch.empty(max(K, 1) * 5, dtype=torch.float64, device=dev)
 
-    def step(prec):
-        eng.eval_eta_dev(wl.numerics, cuts, eta, s2, terms, precision=prec)
+    def step(i, cut):
+        eng.eval_eta_dev(wl.numerics, [cut], eta[i:i + 1], s2[i:i + 1], terms[5 * i:5 * i + 5],
+                         precision=W.PREC_FP64)
 
-    log(f"warmup {args.warmup} step(s), {n_cut} CUTs, grid {args.grid}")
+    mid = n_ch // 2
+    log(f"warmup {args.warmup} step(s) on CUT {mid}; {K} timed steps, one CUT each")
     for _ in range(args.warmup):
-        step(W.PREC_FP32_PHASE64)
+        step(0, mid)
     torch.cuda.synchronize()
-    log("timed steps")
     t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(W.PREC_FP32_PHASE64)
-        log(f"step {i} queued")
+    for i, cut in enumerate(step_cuts):
+        step(i, cut)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    eta32 = eta.cpu().numpy().copy()
-    value = n_cut * args.steps / elapsed
+    log(f"timed: {K} CUTs in {elapsed:.2f} s")
+    eta_steps = eta[:K].cpu().numpy().copy()
+    value = K / elapsed
 
-    # kernel timing with HIP events on the library's stream (one extra step)
+    # kernel timing with HIP events on the library's stream (one extra step, the middle CUT)
     eng.set_profiling(True)
-    step(W.PREC_FP32_PHASE64)
+    step(0, mid)
     torch.cuda.synchronize()
     st = eng.stats()
     eng.set_profiling(False)
-    per_launch_ms = st.region_ms / max(1, st.region_launches)
-    achieved = st.alg_flop / st.region_launches / (per_launch_ms * 1e-3) / 1e12
-    log(f"region kernel {st.region_ms:.1f} ms over {st.region_launches} launch(es); egn {st.egn_ms:.1f} ms; "
-        f"host prep {st.host_prep_ms:.1f} ms; {achieved:.2f} TFLOP/s")
+    roof = kernel_roofline(st, PEAK_FP64_TFLOPS, "region_queue_kernel<double, 0>", HEADLINE_PROFILE)
+    log(f"region kernel {st.region_ms:.1f} ms in {st.region_launches} launch(es); host prep {st.host_prep_ms:.1f} ms; "
+        f"{roof['achieved']:.2f} TFLOP/s ({roof['frac']:.3f} of FP64 peak)")
 
     out = {
         "metric": "CUT NLI coeffs/sec at <=0.01 dB vs FP64 oracle",
         "value": value,
         "unit": "CUT/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": K,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
+        "ms_per_step": 1e3 * elapsed / max(K, 1),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": (f"C+L 10 THz: 100 x 96 GBd on 100 GHz, roll-off 0.04, 20 dBm with +-2 dB tilt, "
-                                f"10 spans U[80,100] km (seed 2), 16QAM/64QAM alternating, EGN on, "
-                                f"{args.grid}x{args.grid} points per square, all {n_cut} CUTs, dz 1 km, "
-                                f"FP32 integrand / FP64 phase and sums"),
-                   "n_cut": int(n_cut), "grid": args.grid, "spans": 10, "channels": 100},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS,
-                     "traffic": args.traffic_bytes if args.traffic_bytes is not None else measured_traffic(),
-                     "kernel": "region_kernel<float, 0>", "per_launch_ms": per_launch_ms,
-                     "alg_flop_per_launch": st.alg_flop / st.region_launches,
-                     # the algorithmic count prices a segment as a complex Horner step (8 FLOP);
-                     # the coefficients are real, so the Goertzel form executes 4 (two FMAs) and
-                     # frac can pass 1; the executed rate against the same peak is frac_executed
-                     "executed_fma_tflops": 4.0 * st.horner_steps / st.region_launches
-                     / (per_launch_ms * 1e-3) / 1e12,
-                     "frac_executed": 4.0 * st.horner_steps / st.region_launches
-                     / (per_launch_ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS},
-        "detail": {"region_ms": st.region_ms, "egn_ms": st.egn_ms, "assemble_ms": st.assemble_ms,
-                   "host_prep_ms": st.host_prep_ms, "squares": st.n_squares,
+        "config": {"workload": ("S+C+L 15 THz: 150 x 100 GBd on 100 GHz, roll-off 0, 24 dBm flat, 40 x 80 km spans "
+                                "with per-span alpha/beta2/beta3/gamma/Cr draws (seed 5), QPSK/16QAM/64QAM, EGN on, "
+                                "1024x1024 points per square, dz 1 km, FP64; one CUT per step, the timed steps "
+                                "spread evenly over the 150 CUTs"),
+                   "cuts_timed": step_cuts, "grid": 1024, "spans": 40, "channels": n_ch},
+        "roofline": roof,
+        "detail": {"region_ms": st.region_ms, "assemble_ms": st.assemble_ms, "host_prep_ms": st.host_prep_ms,
+                   "region_launches": st.region_launches, "squares": st.n_squares,
                    "delta_squares": st.n_delta_squares, "live_points": st.n_points_live,
-                   "horner_steps": st.horner_steps},
+                   "horner_steps": st.horner_steps, "eta_timed_cuts": [float(v) for v in eta_steps]},
     }
-
-    # the host-buffer entry point (CUT list in, eta out through host memory,
-    # synchronous): the same workload with its transfers
-    t1 = time.perf_counter()
-    eng.eval_eta(wl.numerics, cuts, precision=W.PREC_FP32_PHASE64)
-    t_host = time.perf_counter() - t1
-    out["host_buffers"] = {"value": n_cut / t_host, "unit": "CUT/s", "ms_per_step": 1e3 * t_host}
-
-    if not args.no_fp64:
-        # accuracy gate on the full workload: FP32 path vs the FP64 path (the
-        # FP64 path is parity-tested against the oracle); plus its throughput
+    if not args.only_headline:
+        log("accuracy against the oracle")
+        out["accuracy"] = headline_accuracy(eng, W)
+        # the host-buffer entry point (CUT list in, eta out through host memory, synchronous)
+        eng.load(wl)
+        t1 = time.perf_counter()
+        eng.eval_eta(wl.numerics, [mid], precision=W.PREC_FP64)
+        out["host_buffers"] = {"value": 1.0 / (time.perf_counter() - t1), "unit": "CUT/s", "cut": mid}
+        # the same sample with the FP32 integrand (FP64 phases and sums)
+        sample = step_cuts[::max(1, K // 5)]
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        step(W.PREC_FP64)
-        torch.cuda.synchronize()
-        t64 = time.perf_counter() - t1
-        eta64 = eta.cpu().numpy()
-        err = np.abs(10 * np.log10(eta32 / eta64))
-        out["accuracy"] = {"fp32_vs_fp64_max_abs_db": float(err.max()), "fp32_vs_fp64_mean_abs_db": float(err.mean()),
-                           "within_0p01_db": bool(err.max() <= 0.01)}
-        out["fp64_value"] = n_cut / t64
-    if args.integral_cuts > 0:
-        log("integral form leg")
-        out["integral_form"] = integral_form_leg(eng, wl, W, torch, args.integral_cuts)
-    if args.per_cut_dz:
-        out["per_cut_dz"] = per_cut_dz_leg(eng, wl, eta32, W, torch)
-    if args.outer_nf > 1:
-        log("outer-integral leg")
-        out["outer_integral"] = outer_integral_leg(eng, W, torch, n_f=args.outer_nf)
-    if args.mu_map:
-        log("closed-form accuracy map")
-        out["mu_accuracy_map"] = mu_accuracy_map_leg(eng, W, torch)
-    if args.batch_links > 0:
-        out["batched"] = batched_leg(eng, args.batch_links, args.plain_links, W, torch)
-    if args.surrogate_points > 0:
-        log("surrogate leg")
-        out["surrogate"] = surrogate_leg(eng, args.surrogate_points, torch)
+        r32 = eng.eval_eta(wl.numerics, sample, precision=W.PREC_FP32_PHASE64)
+        dt = time.perf_counter() - t1
+        pos = [step_cuts.index(c) for c in sample]
+        out["fp32_phase64"] = {"value": len(sample) / dt, "unit": "CUT/s", "cuts": sample,
+                               "max_abs_db_vs_fp64": float(np.max(np.abs(10 * np.log10(r32["eta"] / eta_steps[pos]))))}
+        log("C+L workload")
+        out["cl_100ch_10span"], wl2, eta32 = cl_leg(eng, W, torch)
+        if args.integral_cuts > 0:
+            log("integral form leg")
+            out["integral_form"] = integral_form_leg(eng, wl2, W, torch, args.integral_cuts)
+        if args.per_cut_dz:
+            out["per_cut_dz"] = per_cut_dz_leg(eng, wl2, eta32, W, torch)
+        if args.outer_nf > 1:
+            log("outer-integral leg")
+            out["outer_integral"] = outer_integral_leg(eng, W, torch, n_f=args.outer_nf)
+        if args.mu_map:
+            log("closed-form accuracy map")
+            out["mu_accuracy_map"] = mu_accuracy_map_leg(eng, W, torch)
+        if args.batch_links > 0:
+            out["batched"] = batched_leg(eng, args.batch_links, args.plain_links, W, torch)
+        if args.surrogate_points > 0:
+            log("surrogate leg")
+            out["surrogate"] = surrogate_leg(eng, args.surrogate_points, torch)
     eng.close()
 
     if args.calib_copy_mib:
@@ -553,7 +707,7 @@ def main():
         torch.cuda.synchronize()
         out["calib_copy_bytes"] = 4 * n
 
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not args.only_headline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_squares)
     print(json.dumps(out), flush=True)

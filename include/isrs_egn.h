@@ -263,18 +263,25 @@ int32_t isrs_batch_eval(isrs_ctx* ctx, isrs_batch* batch, const isrs_numerics* n
 /* As isrs_batch_eval with a device output [n_cuts]; stream-ordered. */
 int32_t isrs_batch_eval_dev(isrs_ctx* ctx, isrs_batch* batch, const isrs_numerics* numerics, double* eta_dev);
 
-/* Launch-shape autotuner: times the candidate region launches (one block per
- * work unit, or persistent blocks per CU in {1, 2, 3} on the queue; natural
- * or cost-sorted order; slice grouping) on this batch, keeps the fastest for
- * the batch, and caches the choice in the JSON file at cache_path (nullable)
- * keyed by architecture, grid size, segment-count and span-count buckets,
- * precision and FWM form.  A cached entry is reused without timing. */
+/* Launch-shape autotuner (the islands are independent work of uneven cost,
+ * Sec. II-B): times candidate region launches on this batch and keeps the
+ * fastest.  Candidates: persistent blocks per CU in {2, 3, 4} on the
+ * cost-sorted queue (and, without format terms, one block per work unit);
+ * the automatic slice grouping or one slice per unit; region-tile geometry:
+ * runs of 2, 4 or 8 points per thread (FP32 segment form; each only where
+ * every slice of 256 runs fits the kernel's staged gain rows).  The work list
+ * is built once and only re-shaped per candidate.  The choice is cached in
+ * the JSON file at cache_path (nullable), keyed by architecture, grid size,
+ * segment-count and span-count buckets, precision and FWM form; a cached
+ * entry is reused without timing. */
 int32_t isrs_autotune(isrs_ctx* ctx, isrs_batch* batch, const isrs_numerics* numerics, const char* cache_path);
 
 /* Launch shape in use on a batch: mode 0 = one block per unit, 1 = queue;
- * blocks_per_cu, sort (1 = cost-sorted) and slices (of 256 point runs) per unit. */
+ * blocks_per_cu, sort (1 = cost-sorted), slices (of 256 point runs) per unit
+ * and points_per_run (0 before the first plan: the precision's default).
+ * Every output pointer is nullable. */
 int32_t isrs_batch_get_tuning(const isrs_batch* batch, int32_t* mode, int32_t* blocks_per_cu, int32_t* sort,
-                              int32_t* slices);
+                              int32_t* slices, int32_t* points_per_run);
 
 /* ------------------------------------------------------------------------
  * Learned surrogate of the per-span FWM efficiency (an MLP ensemble).

@@ -132,7 +132,7 @@ def lib():
     L.isrs_batch_eval.argtypes = [vp, vp, C.POINTER(Numerics_c), dp]
     L.isrs_batch_eval_dev.argtypes = [vp, vp, C.POINTER(Numerics_c), vp]
     L.isrs_autotune.argtypes = [vp, vp, C.POINTER(Numerics_c), C.c_char_p]
-    L.isrs_batch_get_tuning.argtypes = [vp, ip, ip, ip, ip]
+    L.isrs_batch_get_tuning.argtypes = [vp, ip, ip, ip, ip, ip]
     fp = C.POINTER(C.c_float)
     L.isrs_surrogate_create.argtypes = [vp, C.c_int32, C.c_uint64, C.POINTER(vp)]
     L.isrs_surrogate_destroy.argtypes = [vp]
@@ -304,9 +304,10 @@ class Batch:
         return self.tuning()
 
     def tuning(self):
-        v = [C.c_int32() for _ in range(4)]
+        v = [C.c_int32() for _ in range(5)]
         self._e._check(self._e._L.isrs_batch_get_tuning(self._h, *[C.byref(x) for x in v]))
-        return {"mode": v[0].value, "blocks_per_cu": v[1].value, "sort": v[2].value, "slices": v[3].value}
+        return {"mode": v[0].value, "blocks_per_cu": v[1].value, "sort": v[2].value, "slices": v[3].value,
+                "points_per_run": v[4].value}
 
 
 def _fp(a):

@@ -18,6 +18,7 @@
 #include <numeric>
 #include <sstream>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/isrs_egn.h"
@@ -104,11 +105,12 @@ struct Tuning {
     int blocks_per_cu = 0;  // queue mode; 0 = as many as fit
     int sort = 1;           // queue mode: cost-sorted order
     int spb = 0;            // slices per unit; 0 = automatic
+    int ppt = 0;            // points per run (region_ppt_supported); 0 = the precision's default
 };
 
 // Everything one evaluation uploads and launches.
 struct Plan {
-    int N = 0, n_f = 0, AD = 0, n_slices = 0, n_groups = 1, spb = 1;
+    int N = 0, n_f = 0, AD = 0, n_slices = 0, n_groups = 1, spb = 1, ppt = 0;
     bool fp32 = false;
     int mu_method = 0;
     std::vector<LinkDesc> links;
@@ -132,6 +134,16 @@ struct Plan {
     double alg_flop = 0;
     int n_cut_total = 0;
     int queue_blocks = 0;            // persistent blocks of a queue launch
+};
+
+// Squares and instances of some links, before they join a plan.
+struct WorkPart {
+    std::vector<InstDesc> insts;
+    std::vector<SquareItem> items;
+    std::vector<double> item_cost;
+    long long live_points = 0, horner_steps = 0;
+    double alg_flop = 0;
+    int n_cut = 0;
 };
 
 // Device side of a plan.
@@ -286,21 +298,41 @@ double rc(double x, double rs, double ro)
 
 double field_S(double x, double rs, double ro) { return std::sqrt(rc(x, rs, ro)) / rs; }
 
-void plan_begin(const isrs_numerics* nu, Plan& p)
+// Run table of the region kernel: runs of ppt consecutive points along each
+// anti-diagonal m = i + j, and the first run of every anti-diagonal.
+void plan_runs(Plan& p, int ppt)
+{
+    p.ppt = ppt > 0 ? ppt : ppt_of(p.fp32);
+    p.runs.clear();
+    p.adrun.assign(1, 0);
+    for (int m = 0; m < p.AD; ++m) {
+        for (int i = std::max(0, m - p.N + 1); i <= std::min(m, p.N - 1); i += p.ppt)
+            p.runs.push_back(m << RUN_SHIFT | i);
+        p.adrun.push_back((int)p.runs.size());
+    }
+    p.n_slices = (int)((p.runs.size() + THREADS - 1) / THREADS);
+}
+
+// Most anti-diagonals one slice of the run table spans (the kernel stages
+// that many gain rows; NAD at most).
+int plan_max_slice_rows(const Plan& p)
+{
+    int w = 0;
+    for (size_t c0 = 0; c0 < p.runs.size(); c0 += THREADS) {
+        const size_t c1 = std::min(c0 + THREADS, p.runs.size()) - 1;
+        w = std::max(w, (p.runs[c1] >> RUN_SHIFT) - (p.runs[c0] >> RUN_SHIFT) + 1);
+    }
+    return w;
+}
+
+void plan_begin(const isrs_numerics* nu, Plan& p, int ppt = 0)
 {
     p.N = nu->n1;
     p.n_f = nu->n_f;
     p.AD = 2 * p.N - 1;
-    // runs of PPT consecutive points along each anti-diagonal m = i + j
-    p.runs.clear();
-    p.adrun.assign(1, 0);
-    for (int m = 0; m < p.AD; ++m) {
-        for (int i = std::max(0, m - p.N + 1); i <= std::min(m, p.N - 1); i += PPT) p.runs.push_back(m << RUN_SHIFT | i);
-        p.adrun.push_back((int)p.runs.size());
-    }
-    p.n_slices = (int)((p.runs.size() + THREADS - 1) / THREADS);
-    p.fp32 = nu->precision == ISRS_PREC_FP32_PHASE64;
+    p.fp32 = nu->precision == ISRS_PREC_FP32_PHASE64 || nu->mu_method == MU_SUR;
     p.mu_method = nu->mu_method;
+    plan_runs(p, ppt);
 }
 
 // Tables of one link (Eqs. 8-10 / 25 per span, islands per outer sample).
@@ -446,8 +478,10 @@ void plan_link_tables(const LinkInput& L, const isrs_numerics* nu, Plan& p)
 }
 
 // Instances and folded squares of one link's CUTs.
-void plan_link_work(const LinkInput& L, int link, const isrs_numerics* nu, const int32_t* kappa12, int m_explicit,
-                    Plan& p)
+// Squares of one link's instances, appended to w; instance and square
+// indices are offset by inst_base and item_base (their positions in the plan).
+void plan_link_work_into(const LinkInput& L, int link, const isrs_numerics* nu, const int32_t* kappa12,
+                         int m_explicit, const Plan& p, WorkPart& w, int inst_base, int item_base)
 {
     const int nc = L.n_ch, AD = p.AD;
     const LinkDesc& d = p.links[link];
@@ -479,7 +513,7 @@ void plan_link_work(const LinkInput& L, int link, const isrs_numerics* nu, const
             in.link = link;
             in.cut = cut;
             in.nf_idx = n;
-            in.sq_begin = (int)p.items.size();
+            in.sq_begin = item_base + (int)w.items.size();
             const int* lp = &p.livep[d.livep0 + (size_t)n * 3 * (AD + 1)];
             int any_live[3];
             for (int l = 0; l < 3; ++l) any_live[l] = lp[l * (AD + 1) + AD] > 0;
@@ -487,7 +521,7 @@ void plan_link_work(const LinkInput& L, int link, const isrs_numerics* nu, const
                 const int k1 = pr.first, k2 = pr.second;
                 const bool pair_active = L.power[k1] > 0 && L.power[k2] > 0;
                 SquareItem it{};
-                it.inst = (int)p.insts.size();
+                it.inst = inst_base + (int)w.insts.size();
                 it.k1 = k1;
                 it.k2 = k2;
                 it.d_index = -1;
@@ -507,18 +541,81 @@ void plan_link_work(const LinkInput& L, int link, const isrs_numerics* nu, const
                 }
                 if (it.lmask == 0 && !explicit_sq) continue;
                 const long long pts = p.livepts[link][((size_t)n * 8 + it.lmask) * (AD + 1) + AD];
-                p.live_points += pts;
-                p.horner_steps += pts * steps_per_point;
-                p.alg_flop += (double)pts * ksum;
-                p.items.push_back(it);
-                p.item_cost.push_back((double)pts * unit_cost + 1.0);
+                w.live_points += pts;
+                w.horner_steps += pts * steps_per_point;
+                w.alg_flop += (double)pts * ksum;
+                w.items.push_back(it);
+                w.item_cost.push_back((double)pts * unit_cost + 1.0);
             }
-            in.sq_end = (int)p.items.size();
-            p.insts.push_back(in);
+            in.sq_end = item_base + (int)w.items.size();
+            w.insts.push_back(in);
         }
-        p.n_cut_total++;
+        w.n_cut++;
     }
 }
+
+void plan_append(Plan& p, WorkPart& w)
+{
+    p.insts.insert(p.insts.end(), w.insts.begin(), w.insts.end());
+    p.items.insert(p.items.end(), w.items.begin(), w.items.end());
+    p.item_cost.insert(p.item_cost.end(), w.item_cost.begin(), w.item_cost.end());
+    p.live_points += w.live_points;
+    p.horner_steps += w.horner_steps;
+    p.alg_flop += w.alg_flop;
+    p.n_cut_total += w.n_cut;
+    w = WorkPart();
+}
+
+void plan_link_work(const LinkInput& L, int link, const isrs_numerics* nu, const int32_t* kappa12, int m_explicit,
+                    Plan& p)
+{
+    WorkPart w;
+    plan_link_work_into(L, link, nu, kappa12, m_explicit, p, w, (int)p.insts.size(), (int)p.items.size());
+    plan_append(p, w);
+}
+
+// The squares of many links, built on host threads (one contiguous range of
+// links each) and joined in link order, so the plan does not depend on the
+// thread count.
+void plan_links_work_parallel(const std::vector<LinkInput>& Ls, const isrs_numerics* nu, Plan& p)
+{
+    const int n = (int)Ls.size();
+    const int nt = std::max(1, std::min<int>(n, std::min(16u, std::max(1u, std::thread::hardware_concurrency()))));
+    std::vector<WorkPart> parts(n);
+    std::vector<std::thread> th;
+    std::vector<char> failed(nt, 0);
+    for (int t = 0; t < nt; ++t)
+        th.emplace_back([&, t]() {
+            try {
+                for (int l = (int)((long long)n * t / nt); l < (int)((long long)n * (t + 1) / nt); ++l)
+                    plan_link_work_into(Ls[l], l, nu, nullptr, 0, p, parts[l], 0, 0);
+            } catch (...) {
+                failed[t] = 1;
+            }
+        });
+    for (auto& x : th) x.join();
+    for (char f : failed)
+        if (f) throw std::bad_alloc();
+    size_t n_items = p.items.size(), n_insts = p.insts.size();
+    for (const WorkPart& w : parts) {
+        n_items += w.items.size();
+        n_insts += w.insts.size();
+    }
+    p.items.reserve(n_items);
+    p.item_cost.reserve(n_items);
+    p.insts.reserve(n_insts);
+    for (WorkPart& w : parts) {
+        const int ib = (int)p.insts.size(), sb = (int)p.items.size();
+        for (SquareItem& it : w.items) it.inst += ib;
+        for (InstDesc& in : w.insts) {
+            in.sq_begin += sb;
+            in.sq_end += sb;
+        }
+        plan_append(p, w);
+    }
+}
+
+
 
 // Coherent-sum rows, launch chunks (surrogate tables only), slice groups and
 // queue order.  A plan with coherent sums always runs on the queue: each of
@@ -633,6 +730,7 @@ std::string plan_check(const Plan& p)
     }
     for (int r : p.runs)
         if ((r >> RUN_SHIFT) >= p.AD || (r & RUN_MASK) >= p.N) return "run out of the grid";
+    if (!region_ppt_supported(p.fp32, p.mu_method, p.ppt)) return "no kernel for this run length";
     if (p.adrun.size() != (size_t)p.AD + 1 || p.adrun.back() != (int)p.runs.size()) return "anti-diagonal run table";
     for (int m = 0; m < p.AD; ++m)
         if (p.adrun[m] >= p.adrun[m + 1] || (p.runs[p.adrun[m]] >> RUN_SHIFT) != m ||
@@ -650,7 +748,7 @@ void plan_queue_shape(const isrs_ctx* c, Plan& p)
 {
     p.queue_blocks = 0;
     if (p.tu.mode != 1) return;
-    const int per_cu = region_blocks_per_cu(p.fp32, p.mu_method);
+    const int per_cu = region_blocks_per_cu(p.fp32, p.mu_method, p.ppt);
     p.queue_blocks = std::max(1, c->n_cu) * (p.tu.blocks_per_cu > 0 ? std::min(p.tu.blocks_per_cu, per_cu) : per_cu);
 }
 
@@ -847,7 +945,7 @@ int32_t plan_enqueue(isrs_ctx* c, Workspace& w, const Plan& p, hipStream_t st, d
             if ((rc = sf->fill(c, ra, b, e, p.links[0].n_sp, sur_tab, st))) return rc;
         }
         if ((rc = mark(ev_reg, true))) return rc;
-        HIP_TRY(c, launch_region(ra, blocks, p.fp32, st));
+        HIP_TRY(c, launch_region(ra, blocks, p.fp32, p.ppt, st));
         if ((rc = mark(ev_reg, false))) return rc;
     }
     if (assemble) {
@@ -1113,7 +1211,10 @@ bool same_numerics(const isrs_numerics& a, const isrs_numerics& b)
            a.precision == b.precision && a.mu_method == b.mu_method;
 }
 
-int32_t batch_plan(isrs_ctx* c, isrs_batch* b, const isrs_numerics* nu)
+// Plans a batch for the numerics nu and the batch's tuning.  With reuse, a plan
+// built for the same numerics keeps its tables and squares and only takes the
+// new launch shape (run length, slice groups, queue order, grid).
+int32_t batch_plan(isrs_ctx* c, isrs_batch* b, const isrs_numerics* nu, bool reuse = false)
 {
     std::string m = validate_numerics_msg(nu);
     if (!m.empty()) return fail(c, ISRS_E_ARG, m);
@@ -1121,22 +1222,22 @@ int32_t batch_plan(isrs_ctx* c, isrs_batch* b, const isrs_numerics* nu)
         m = validate_link_numerics(b->link(l), nu);
         if (!m.empty()) return fail(c, ISRS_E_ARG, "link " + std::to_string(l) + ": " + m);
     }
+    const bool keep = reuse && b->planned && same_numerics(b->key, *nu);
     b->drop_graph();
     b->planned = false;
     Plan p;
     try {
-        plan_begin(nu, p);
-        size_t est = 0;
-        for (int l = 0; l < b->n_links; ++l) {
-            const LinkInput L = b->link(l);
-            size_t act = 0;
-            for (int k = 0; k < L.n_ch; ++k) act += L.power[k] > 0;
-            est += (size_t)L.n_cut * p.n_f * act * (act + 1) / 2;
+        if (keep) {
+            p = std::move(b->plan);
+            plan_runs(p, b->tuning.ppt);
+        } else {
+            plan_begin(nu, p, b->tuning.ppt);
+            std::vector<LinkInput> Ls;
+            for (int l = 0; l < b->n_links; ++l) Ls.push_back(b->link(l));
+            for (int l = 0; l < b->n_links; ++l) plan_link_tables(Ls[l], nu, p);
+            plan_links_work_parallel(Ls, nu, p);
         }
-        p.items.reserve(est);
-        p.item_cost.reserve(est);
-        for (int l = 0; l < b->n_links; ++l) plan_link_tables(b->link(l), nu, p);
-        for (int l = 0; l < b->n_links; ++l) plan_link_work(b->link(l), l, nu, nullptr, 0, p);
+        if (plan_max_slice_rows(p) > NAD) return fail(c, ISRS_E_ARG, "run length too long for this grid");
         plan_finish(p, b->tuning);
         plan_queue_shape(c, p);
     } catch (const std::bad_alloc&) {
@@ -1211,18 +1312,19 @@ std::map<std::string, std::vector<double>> read_cache(const char* path)
     std::ifstream f(path);
     std::string line;
     while (std::getline(f, line)) {
-        // {"key": "...", "mode": m, "blocks_per_cu": b, "sort": s, "slices": p, "ms": t}
+        // {"key": "...", "mode": m, "blocks_per_cu": b, "sort": s, "slices": p, "ppt": r, "ms": t}
         auto kpos = line.find("\"key\": \"");
         if (kpos == std::string::npos) continue;
         auto kend = line.find('"', kpos + 8);
         std::string key = line.substr(kpos + 8, kend - kpos - 8);
         std::vector<double> v;
-        for (const char* name : {"\"mode\": ", "\"blocks_per_cu\": ", "\"sort\": ", "\"slices\": ", "\"ms\": "}) {
+        for (const char* name :
+             {"\"mode\": ", "\"blocks_per_cu\": ", "\"sort\": ", "\"slices\": ", "\"ppt\": ", "\"ms\": "}) {
             auto p = line.find(name);
             if (p == std::string::npos) break;
             v.push_back(std::atof(line.c_str() + p + std::strlen(name)));
         }
-        if (v.size() == 5) out[key] = v;
+        if (v.size() == 6) out[key] = v;
     }
     return out;
 }
@@ -1237,7 +1339,8 @@ bool write_cache(const char* path, const std::map<std::string, std::vector<doubl
     for (auto& kv : m) {
         f << "{\"key\": \"" << kv.first << "\", \"mode\": " << (int)kv.second[0]
           << ", \"blocks_per_cu\": " << (int)kv.second[1] << ", \"sort\": " << (int)kv.second[2]
-          << ", \"slices\": " << (int)kv.second[3] << ", \"ms\": " << kv.second[4] << "}"
+          << ", \"slices\": " << (int)kv.second[3] << ", \"ppt\": " << (int)kv.second[4]
+          << ", \"ms\": " << kv.second[5] << "}"
           << (++i < m.size() ? ",\n" : "\n");
     }
     f << "]\n";
@@ -1833,7 +1936,8 @@ int32_t isrs_batch_eval(isrs_ctx* c, isrs_batch* b, const isrs_numerics* nu, dou
     }
 }
 
-int32_t isrs_batch_get_tuning(const isrs_batch* b, int32_t* mode, int32_t* bpc, int32_t* sort, int32_t* slices)
+int32_t isrs_batch_get_tuning(const isrs_batch* b, int32_t* mode, int32_t* bpc, int32_t* sort, int32_t* slices,
+                              int32_t* points_per_run)
 {
     try {
         if (!b) return ISRS_E_ARG;
@@ -1842,6 +1946,7 @@ int32_t isrs_batch_get_tuning(const isrs_batch* b, int32_t* mode, int32_t* bpc, 
         if (bpc) *bpc = t.blocks_per_cu;
         if (sort) *sort = t.sort;
         if (slices) *slices = b->planned ? b->plan.spb : b->tuning.spb;
+        if (points_per_run) *points_per_run = b->planned ? b->plan.ppt : b->tuning.ppt;
         return ISRS_OK;
     } catch (...) {
         return abi_exception(nullptr);
@@ -1865,32 +1970,39 @@ int32_t isrs_autotune(isrs_ctx* c, isrs_batch* b, const isrs_numerics* nu, const
         auto cache = read_cache(cache_path);
         auto hit = cache.find(key);
         if (hit != cache.end()) {
-            b->tuning = {(int)hit->second[0], (int)hit->second[1], (int)hit->second[2], (int)hit->second[3]};
-            b->planned = false;
-            b->drop_graph();
-            return batch_plan(c, b, nu);
+            const auto& v = hit->second;
+            b->tuning = {(int)v[0], (int)v[1], (int)v[2], (int)v[3], (int)v[4]};
+            return batch_plan(c, b, nu, true);
         }
-        // candidates: grid mode at one slice or all slices of a square per
-        // unit, queue mode with 1..4 blocks per CU, sorted and natural order
+        // candidates: queue mode (the only one for coherent sums) with 2..4
+        // blocks per CU, the automatic slice grouping or one slice per unit,
+        // and every run length with a kernel instance whose slices fit the
+        // staged rows; without format terms also the grid mode
         Plan shape;
         plan_begin(nu, shape);
-        const int ns = shape.n_slices;
-        std::vector<Tuning> cands;
-        for (int spb : {1, ns}) {
-            cands.push_back({0, 0, 0, spb});
-            for (int bpc : {1, 2, 3, 4})
-                for (int sort : {1, 0}) cands.push_back({1, bpc, sort, spb});
-            if (ns == 1) break;
+        std::vector<int> ppts;
+        for (int r : {ppt_of(shape.fp32), 2, 4, 8}) {
+            if (std::find(ppts.begin(), ppts.end(), r) != ppts.end()) continue;
+            if (!region_ppt_supported(shape.fp32, nu->mu_method, r)) continue;
+            plan_runs(shape, r);
+            if (plan_max_slice_rows(shape) <= NAD) ppts.push_back(r);
         }
+        std::vector<Tuning> cands;
+        for (int r : ppts)
+            for (int spb : {0, 1}) {
+                if (!nu->egn) cands.push_back({0, 0, 0, spb, r});
+                for (int bpc : {4, 3, 2}) cands.push_back({1, bpc, 1, spb, r});
+            }
         const bool prof = c->profiling;
         c->profiling = true;
         double best = 1e300;
         Tuning best_t = b->tuning;
+        bool first = true;
         for (const Tuning& t : cands) {
             b->tuning = t;
-            b->planned = false;
-            int32_t rc = batch_plan(c, b, nu);
-            if (!rc) rc = batch_run(c, b, b->out.as<double>(), false);  // warm
+            int32_t rc = batch_plan(c, b, nu, true);
+            if (!rc && first) rc = batch_run(c, b, b->out.as<double>(), false);  // loads the kernels
+            first = false;
             if (!rc) rc = batch_run(c, b, b->out.as<double>(), false);
             if (rc) {
                 c->profiling = prof;
@@ -1904,10 +2016,10 @@ int32_t isrs_autotune(isrs_ctx* c, isrs_batch* b, const isrs_numerics* nu, const
         }
         c->profiling = prof;
         b->tuning = best_t;
-        b->planned = false;
-        int32_t rc = batch_plan(c, b, nu);
+        int32_t rc = batch_plan(c, b, nu, true);
         if (rc) return rc;
-        cache[key] = {(double)best_t.mode, (double)best_t.blocks_per_cu, (double)best_t.sort, (double)b->plan.spb, best};
+        cache[key] = {(double)best_t.mode, (double)best_t.blocks_per_cu, (double)best_t.sort, (double)best_t.spb,
+                      (double)b->plan.ppt, best};
         if (!write_cache(cache_path, cache)) return fail(c, ISRS_E_ARG, "cannot write the autotune cache file");
         return ISRS_OK;
     } catch (...) {

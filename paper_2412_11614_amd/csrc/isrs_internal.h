@@ -11,11 +11,16 @@
 namespace isrs {
 
 // Region kernel: 256 threads; each owns a run of PPT consecutive points of
-// one anti-diagonal of the N x N grid.  Runs are listed by anti-diagonal, and
-// a slice (THREADS consecutive runs) spans at most NAD anti-diagonals for
-// every N (59 at most, at N = 30), which bounds the staged LDS rows.
+// one anti-diagonal of the N x N grid (per precision; 4 in both: 2-point runs
+// in FP64 fit four waves per SIMD but ran 4% slower at three and 18% slower at
+// four, with twice the slices to stage).  Runs are listed by anti-diagonal,
+// and a slice (THREADS consecutive runs) spans at most NAD anti-diagonals for
+// every N (59 at most, at N = 30, with 4-point runs; 43 with 2-point runs),
+// which bounds the staged LDS rows.
 constexpr int THREADS = 256;
-constexpr int PPT = 4;                // points per run
+constexpr int PPT32 = 4;              // points per run, FP32 integrand
+constexpr int PPT64 = 4;              // points per run, FP64
+constexpr int ppt_of(bool fp32) { return fp32 ? PPT32 : PPT64; }
 constexpr int NAD = 63;               // staged anti-diagonal rows per slice
 constexpr int RUN_SHIFT = 13;         // run = m << RUN_SHIFT | first column, N <= 8192
 constexpr int RUN_MASK = (1 << RUN_SHIFT) - 1;
@@ -168,10 +173,11 @@ hipError_t noalloc_scratch(int device, void** ptr);
 
 // Kernel launchers (isrs_kernels.hip).  blocks = 0 launches one block per
 // unit; blocks > 0 launches that many persistent blocks on the queue.
-hipError_t launch_region(const RegionArgs& a, int blocks, bool fp32, hipStream_t st);
+hipError_t launch_region(const RegionArgs& a, int blocks, bool fp32, int ppt, hipStream_t st);
+bool region_ppt_supported(bool fp32, int mu_method, int ppt);   // points per run with a kernel instance
 hipError_t launch_zero_counter(int* counter, hipStream_t st);
 hipError_t launch_assemble(const AssembleArgs& a, hipStream_t st);
-int region_blocks_per_cu(bool fp32, int mu_method);
+int region_blocks_per_cu(bool fp32, int mu_method, int ppt);
 
 }  // namespace isrs
 

@@ -85,9 +85,39 @@ __device__ __forceinline__ void sincos_rev(float t, float* s, float* c)
     *c = __builtin_amdgcn_cosf(t);
 }
 
+// Sine and cosine of 2 pi t for a phase t in revolutions (|t| <= 1 here), in
+// FP64: t = k/4 + r with k the nearest quarter turn, so |r| <= 1/8 exactly;
+// the Taylor series of sin and cos at x = 2 pi r (|x| <= pi/4) through x^17
+// and x^18 (the first omitted terms are below 1e-19), then a rotation by k
+// quarter turns.
 __device__ __forceinline__ void sincos_rev(double t, double* s, double* c)
 {
-    sincospi(2.0 * t, s, c);
+    const double k = rint(4.0 * t);
+    const double x = (t - 0.25 * k) * 6.283185307179586476925286766559;
+    const double x2 = x * x;
+    double ps = 2.8114572543455206e-15;          // 1/17!
+    ps = fma(ps, x2, -7.6471637318198164e-13);   // 1/15!
+    ps = fma(ps, x2, 1.6059043836821613e-10);    // 1/13!
+    ps = fma(ps, x2, -2.5052108385441720e-08);   // 1/11!
+    ps = fma(ps, x2, 2.7557319223985893e-06);    // 1/9!
+    ps = fma(ps, x2, -1.9841269841269841e-04);   // 1/7!
+    ps = fma(ps, x2, 8.3333333333333333e-03);    // 1/5!
+    ps = fma(ps, x2, -1.6666666666666667e-01);   // 1/3!
+    const double sx = fma(x * x2, ps, x);
+    double pc = 1.5619206968586225e-16;          // 1/18!
+    pc = fma(pc, x2, -4.7794773323873853e-14);   // 1/16!
+    pc = fma(pc, x2, 1.1470745597729725e-11);    // 1/14!
+    pc = fma(pc, x2, -2.0876756987868099e-09);   // 1/12!
+    pc = fma(pc, x2, 2.7557319223985891e-07);    // 1/10!
+    pc = fma(pc, x2, -2.4801587301587302e-05);   // 1/8!
+    pc = fma(pc, x2, 1.3888888888888889e-03);    // 1/6!
+    pc = fma(pc, x2, -4.1666666666666667e-02);   // 1/4!
+    pc = fma(pc, x2, 0.5);                       // 1/2!
+    const double cx = fma(-x2, pc, 1.0);
+    const int q = (int)k & 3;
+    const double s1 = (q & 1) ? cx : sx, c1 = (q & 1) ? sx : cx;
+    *s = (q & 2) ? -s1 : s1;
+    *c = ((q + 1) & 2) ? -c1 : c1;
 }
 
 __device__ __forceinline__ float exp_r(float x) { return expf(x); }
@@ -112,9 +142,16 @@ __device__ __forceinline__ float exp_neg(float zeta, double x)
 }
 __device__ __forceinline__ double exp_neg(double zeta, double x) { return exp(-zeta * x); }
 
-// 1 / x: FP32 hardware reciprocal (1 ulp), FP64 division
+// 1 / x of a positive normal x: FP32 hardware reciprocal (1 ulp); FP64 the
+// hardware approximation refined by two Newton steps (each squares the
+// relative error)
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+__device__ __forceinline__ double recip(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(fma(-x, r, 1.0), r, r);
+    return fma(fma(-x, r, 1.0), r, r);
+}
 
 // t - floor(t) of a phase in revolutions, then in the working precision
 template <typename R>
@@ -247,7 +284,7 @@ __device__ __forceinline__ void node_weight(int n, const R (&mr)[4], const R (&m
 // accumulator slot in FP64.  Row and column j belong to thread j mod THREADS,
 // anti-diagonal m to thread m mod THREADS, in every slice and square, so no
 // two threads ever touch one accumulator and the result is deterministic.
-template <typename R>
+template <typename R, int PPT>
 __device__ void egn_slice(const int em, const int N, const int c0, const int c1, const int mlo, const int mhi,
                           const int m, const int i0, const int ihi, const bool has, const R (&ur)[PPT],
                           const R (&ui)[PPT], const double* Sg, const double* wt, const double* s3,
@@ -394,7 +431,7 @@ __device__ void egn_finish(const int em, const int N, const double h, const doub
 // The span, run and live tables are read through restrict-qualified kernel
 // parameters: nothing the kernel writes aliases them, so their block-uniform
 // reads go through scalar loads.
-template <typename R, int MU>
+template <typename R, int MU, int PPT>
 __device__ void region_unit(const RegionArgs& a, const int u, const int slot, VecOf<R>* g_vec, double* red,
                             const SpanConst* __restrict__ spans_all, const int* __restrict__ runs,
                             const int* __restrict__ livep_all)
@@ -679,7 +716,7 @@ __device__ void region_unit(const RegionArgs& a, const int u, const int slot, Ve
         }
 
         if (acc)
-            egn_slice<R>(it.egn_mask, N, c0, c1, mlo, mhi, m, i0, ihi, has, ur, ui, Sg, wt, s3, a.adrun, g_vec,
+            egn_slice<R, PPT>(it.egn_mask, N, c0, c1, mlo, mhi, m, i0, ihi, has, ur, ui, Sg, wt, s3, a.adrun, g_vec,
                          acc);
 
         // GN island sums (Eq. 17)
@@ -710,17 +747,17 @@ __device__ void region_unit(const RegionArgs& a, const int u, const int slot, Ve
 }
 
 // Waves per SIMD the register budget is set for: FP32 at most 128 VGPRs (four
-// waves), 168 for the FP32 integral form (three); FP64 168 for the segment
-// form (three, a few spills beat two waves), otherwise two.
-template <typename R, int MU>
+// waves), 168 for the FP32 integral form and 8-point runs (three); FP64 168
+// for the segment form (three, a few spills beat two waves), otherwise two.
+template <typename R, int MU, int PPT>
 constexpr int region_min_waves()
 {
-    if constexpr (sizeof(R) == 4) return MU == MU_INT ? 3 : 4;
+    if constexpr (sizeof(R) == 4) return (MU == MU_INT || PPT > 4) ? 3 : 4;
     else return MU == MU_SEG ? 3 : 2;
 }
 
-template <typename R, int MU>
-__global__ void __launch_bounds__(THREADS, (region_min_waves<R, MU>())) region_kernel(RegionArgs a, const SpanConst* __restrict__ spans,
+template <typename R, int MU, int PPT>
+__global__ void __launch_bounds__(THREADS, (region_min_waves<R, MU, PPT>())) region_kernel(RegionArgs a, const SpanConst* __restrict__ spans,
                                                                                    const int* __restrict__ runs,
                                                                                    const int* __restrict__ livep)
 {
@@ -729,13 +766,13 @@ __global__ void __launch_bounds__(THREADS, (region_min_waves<R, MU>())) region_k
     static_assert(sizeof(g_vec) >= THREADS * PPT * sizeof(typename Prec<R>::V2) + THREADS * sizeof(double2) +
                                        3 * NAD * sizeof(double) + (NAD + 1) * sizeof(int),
                   "the coherent-sum staging must fit in the gain rows");
-    region_unit<R, MU>(a, a.unit0 + blockIdx.x, -1, g_vec, red, spans, runs, livep);
+    region_unit<R, MU, PPT>(a, a.unit0 + blockIdx.x, -1, g_vec, red, spans, runs, livep);
 }
 
 // Persistent blocks on a queue: every block pops unit positions until the
 // launch's units are exhausted, so every block reaches the exit.
-template <typename R, int MU>
-__global__ void __launch_bounds__(THREADS, (region_min_waves<R, MU>())) region_queue_kernel(RegionArgs a, const SpanConst* __restrict__ spans,
+template <typename R, int MU, int PPT>
+__global__ void __launch_bounds__(THREADS, (region_min_waves<R, MU, PPT>())) region_queue_kernel(RegionArgs a, const SpanConst* __restrict__ spans,
                                                                                          const int* __restrict__ runs,
                                                                                          const int* __restrict__ livep)
 {
@@ -750,7 +787,7 @@ __global__ void __launch_bounds__(THREADS, (region_min_waves<R, MU>())) region_q
         const int pos = pos_s;
         __syncthreads();
         if (pos < 0 || pos >= a.n_units) break;
-        region_unit<R, MU>(a, a.order[a.unit0 + pos], blockIdx.x, g_vec, red, spans, runs, livep);
+        region_unit<R, MU, PPT>(a, a.order[a.unit0 + pos], blockIdx.x, g_vec, red, spans, runs, livep);
     }
 }
 
@@ -835,28 +872,42 @@ __global__ void __launch_bounds__(THREADS) assemble_kernel(AssembleArgs a)
 
 }  // namespace
 
-template <typename R, int MU>
+template <typename R, int MU, int PPT = (sizeof(R) == 4 ? PPT32 : PPT64)>
 hipError_t launch_region_t(const RegionArgs& a, int blocks, hipStream_t st)
 {
     if (blocks > 0)
-        hipLaunchKernelGGL((region_queue_kernel<R, MU>), dim3(blocks), dim3(THREADS), 0, st, a, a.spans, a.runs, a.livep);
+        hipLaunchKernelGGL((region_queue_kernel<R, MU, PPT>), dim3(blocks), dim3(THREADS), 0, st, a, a.spans, a.runs,
+                           a.livep);
     else
-        hipLaunchKernelGGL((region_kernel<R, MU>), dim3(a.n_units), dim3(THREADS), 0, st, a, a.spans, a.runs, a.livep);
+        hipLaunchKernelGGL((region_kernel<R, MU, PPT>), dim3(a.n_units), dim3(THREADS), 0, st, a, a.spans, a.runs,
+                           a.livep);
     return hipGetLastError();
 }
 
-hipError_t launch_region(const RegionArgs& a, int blocks, bool fp32, hipStream_t st)
+bool region_ppt_supported(bool fp32, int mu_method, int ppt)
+{
+    if (ppt == ppt_of(fp32)) return true;
+    return fp32 && mu_method == MU_SEG && (ppt == 2 || ppt == 8);
+}
+
+hipError_t launch_region(const RegionArgs& a, int blocks, bool fp32, int ppt, hipStream_t st)
 {
     if (a.n_units == 0) return hipSuccess;
+    if (!region_ppt_supported(fp32, a.mu_method, ppt)) return hipErrorInvalidValue;
     if (a.mu_method == MU_SUR) {
         if (!fp32 || !a.sur_tab) return hipErrorInvalidValue;   // the table path runs the FP32 integrand
         return launch_region_t<float, MU_SUR>(a, blocks, st);
     }
     if (a.mu_method == MU_INT)
         return fp32 ? launch_region_t<float, MU_INT>(a, blocks, st) : launch_region_t<double, MU_INT>(a, blocks, st);
-    if (fp32)
-        return a.mu_method == 0 ? launch_region_t<float, 0>(a, blocks, st) : launch_region_t<float, 1>(a, blocks, st);
-    return a.mu_method == 0 ? launch_region_t<double, 0>(a, blocks, st) : launch_region_t<double, 1>(a, blocks, st);
+    if (fp32) {
+        if (a.mu_method == MU_MAC) return launch_region_t<float, MU_MAC>(a, blocks, st);
+        if (ppt == 2) return launch_region_t<float, MU_SEG, 2>(a, blocks, st);
+        if (ppt == 8) return launch_region_t<float, MU_SEG, 8>(a, blocks, st);
+        return launch_region_t<float, MU_SEG>(a, blocks, st);
+    }
+    return a.mu_method == MU_SEG ? launch_region_t<double, MU_SEG>(a, blocks, st)
+                                 : launch_region_t<double, MU_MAC>(a, blocks, st);
 }
 
 hipError_t launch_zero_counter(int* counter, hipStream_t st)
@@ -866,22 +917,25 @@ hipError_t launch_zero_counter(int* counter, hipStream_t st)
 }
 
 // Resident blocks per CU of the queue kernel (occupancy query).
-int region_blocks_per_cu(bool fp32, int mu_method)
+template <typename R, int MU, int PPT = (sizeof(R) == 4 ? PPT32 : PPT64)>
+int queue_occupancy()
 {
     int n = 0;
-    hipError_t e;
-    if (mu_method == MU_SUR)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, region_queue_kernel<float, MU_SUR>, THREADS, 0);
-    else if (mu_method == MU_INT)
-        e = fp32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, region_queue_kernel<float, MU_INT>, THREADS, 0)
-                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, region_queue_kernel<double, MU_INT>, THREADS, 0);
-    else if (fp32)
-        e = mu_method == 0 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, region_queue_kernel<float, 0>, THREADS, 0)
-                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, region_queue_kernel<float, 1>, THREADS, 0);
-    else
-        e = mu_method == 0 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, region_queue_kernel<double, 0>, THREADS, 0)
-                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, region_queue_kernel<double, 1>, THREADS, 0);
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, region_queue_kernel<R, MU, PPT>, THREADS, 0);
     return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+int region_blocks_per_cu(bool fp32, int mu_method, int ppt)
+{
+    if (mu_method == MU_SUR) return queue_occupancy<float, MU_SUR>();
+    if (mu_method == MU_INT) return fp32 ? queue_occupancy<float, MU_INT>() : queue_occupancy<double, MU_INT>();
+    if (fp32) {
+        if (mu_method == MU_MAC) return queue_occupancy<float, MU_MAC>();
+        if (ppt == 2) return queue_occupancy<float, MU_SEG, 2>();
+        if (ppt == 8) return queue_occupancy<float, MU_SEG, 8>();
+        return queue_occupancy<float, MU_SEG>();
+    }
+    return mu_method == MU_SEG ? queue_occupancy<double, MU_SEG>() : queue_occupancy<double, MU_MAC>();
 }
 
 hipError_t launch_assemble(const AssembleArgs& a, hipStream_t st)

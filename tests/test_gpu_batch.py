@@ -115,16 +115,22 @@ def test_autotune_picks_a_shape_and_caches_it(engine, tmp_path):
     engine.set_profiling(False)
     cache = str(tmp_path / "tune.json")
     t = b.autotune(nu, cache, precision=FP32)
-    assert t["mode"] in (0, 1) and t["slices"] >= 1
+    print("tuned shape", t, flush=True)
+    assert t["mode"] in (0, 1) and t["slices"] >= 1 and t["points_per_run"] in (2, 4, 8)
     entries = json.load(open(cache))
-    assert len(entries) == 1 and entries[0]["ms"] > 0
+    assert len(entries) == 1 and entries[0]["ms"] > 0 and entries[0]["ppt"] == t["points_per_run"]
     got = b.eval(nu, precision=FP32)
-    assert np.allclose(got, ref, rtol=1e-12, atol=0)
-    # a second batch of the same shape reuses the cached choice
+    if t["points_per_run"] == 4:
+        # the same runs: only the launch shape and the grouping of partial sums change
+        assert np.allclose(got, ref, rtol=1e-12, atol=0)
+    else:
+        # other runs stage the gain rows from other anti-diagonals: FP32 rounding only
+        assert np.max(np.abs(10 * np.log10(got / ref))) <= 1e-4
+    # a second batch of the same shape reuses the cached choice, with the same results
     b2 = engine.batch(links)
     t2 = b2.autotune(nu, cache, precision=FP32)
     assert t2 == t
-    assert np.allclose(b2.eval(nu, precision=FP32), ref, rtol=1e-12, atol=0)
+    assert np.array_equal(b2.eval(nu, precision=FP32), got)
     b.close()
     b2.close()
 
