@@ -115,14 +115,14 @@ def cpu_baseline(wl, n_squares, seed=0):
                 continue
             if any(0 <= k1 + k2 - cut + l < nc and act[k1 + k2 - cut + l] for l in (-1, 0, 1)):
                 live.append((k1, k2))
-    rng = np.random.default_rng(seed)
-    pick = [live[i] for i in rng.choice(len(live), size=n_squares, replace=False)]
     cores = os.cpu_count() or 1
     try:
         cores = len(os.sched_getaffinity(0))
     except AttributeError:
         pass
-    n_squares = n_squares or cores
+    n_squares = n_squares or min(cores, 16)
+    rng = np.random.default_rng(seed)
+    pick = [live[i] for i in rng.choice(len(live), size=n_squares, replace=False)]
     threads = max(1, min(cores, n_squares))
     t0 = time.perf_counter()
     with cf.ThreadPoolExecutor(threads) as ex:
@@ -135,7 +135,7 @@ def cpu_baseline(wl, n_squares, seed=0):
                        f"integral-form mu; {wall:.1f} s wall on {threads} threads, scaled by squares per CUT")}
 
 
-def batched_leg(eng, n_links, n_plain, W, torch, tune_links=64):
+def batched_leg(eng, n_links, n_plain, W, torch, tune_links=32):
     """Uneven-link workload in one persistent queue launch, replayed from a
     captured graph, with the launch shape from the project's autotuner (tuned
     on the batch's first tune_links links, whose shape key the full batch
@@ -473,7 +473,7 @@ def _gold(stage):
 def headline_accuracy(eng, W):
     """The headline path (FP64, segment form) on the S+C+L workload against
     stored oracle values of the model (integral form, adaptive quadrature):
-    per-CUT eta at 64 x 64 (8 seeded CUTs) and 128 x 128 (CUTs 0, 75), and the
+    per-CUT eta at 64 x 64 (4 seeded CUTs) and 128 x 128 (CUTs 0, 75), and the
     GN sums of every near-CUT square of four CUTs at the full 1024 x 1024 grid
     (an oracle CUT at that grid is out of reach; the near squares carry most of
     its eta)."""
@@ -513,7 +513,7 @@ def headline_accuracy(eng, W):
 def cl_leg(eng, W, torch, reps=2):
     """The C+L workload (100 x 96 GBd, 10 spans, 256 x 256 per square): all 100
     CUTs per step in the FP32-integrand / FP64-phase variant and in FP64, with
-    both against stored oracle values (8 CUTs at 256 x 256, all CUTs at 64 x 64)."""
+    both against stored oracle values (CUTs 0/49/99 at 256 x 256, all CUTs at 64 x 64)."""
     wl = W.cl_100ch_10span(n_grid=256)
     cuts = wl.cuts
     n = len(cuts)
@@ -561,14 +561,90 @@ def cl_leg(eng, W, torch, reps=2):
     return res, wl, out_eta[W.PREC_FP32_PHASE64]
 
 
+def profile_run(args, torch, _lib, W):
+    """Timed steps of one other kernel, for its counter runs: the C+L workload
+    (region_queue_kernel<float, 0>) or the surrogate's fused inference
+    (mlp_fused_kernel).  Prints one JSON line with the HIP-event times."""
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    eng = _lib.Engine(0, stream=stream)
+    out = {"workload": args.workload, "steps": args.steps}
+    if args.workload == "cl":
+        wl = W.cl_100ch_10span(n_grid=256)
+        eng.load(wl)
+        eta = torch.empty(len(wl.cuts), dtype=torch.float64, device="cuda")
+        for _ in range(args.warmup):
+            eng.eval_eta_dev(wl.numerics, wl.cuts, eta, precision=W.PREC_FP32_PHASE64)
+        torch.cuda.synchronize()
+        eng.set_profiling(True)
+        ms = []
+        for _ in range(args.steps):
+            eng.eval_eta_dev(wl.numerics, wl.cuts, eta, precision=W.PREC_FP32_PHASE64)
+            torch.cuda.synchronize()
+            st = eng.stats()
+            ms.append(st.region_ms)
+        out["roofline"] = kernel_roofline(st, PEAK_FP32_TFLOPS, "region_queue_kernel<float, 0>", CL_PROFILE)
+        out["region_ms"] = ms
+    elif args.workload == "batch":
+        links = W.batch_links()
+        nu = links[0].numerics
+        b = eng.batch(links)
+        eta = torch.empty(b.n_cuts, dtype=torch.float64, device="cuda")
+        for _ in range(max(2, args.warmup)):      # eager run, then the graph capture
+            b.eval_dev(nu, eta)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            b.eval_dev(nu, eta)
+        torch.cuda.synchronize()
+        out.update({"n_cut": b.n_cuts, "ms_per_step": 1e3 * (time.perf_counter() - t0) / max(1, args.steps),
+                    "shape": b.tuning()})
+        b.close()
+    else:
+        n = 1 << 22
+        x = torch.empty(n, 16, device="cuda")
+        r = torch.empty(n, device="cuda")
+        eng.surrogate_datagen(x, r, 4)
+        s = eng.surrogate(4, seed=4)
+        s.train(x, r, steps=200, batch=1024, lr=1e-3)
+        y = torch.empty(n, device="cuda")
+        for _ in range(args.warmup):
+            s.eval_points(x, y, float("inf"))
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record(stream)
+        for _ in range(args.steps):
+            s.eval_points(x, y, float("inf"))
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        dt = ev[0].elapsed_time(ev[1]) * 1e-3 / max(1, args.steps)
+        flop = 2 * (16 * 256 + 3 * 256 * 256 + 256) * 4 * n
+        out.update({"points": n, "ms_per_call": 1e3 * dt, "points_per_s": n / dt,
+                    "mfma_tflops": flop / dt / 1e12, "frac_bf16_peak": flop / dt / 1e12 / 2500.0})
+        s.close()
+    eng.close()
+    if args.calib_copy_mib:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = 4 * n
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-squares", type=int, default=0,
-                    help="oracle squares of the CPU baseline (0: one per host thread)")
+                    help="oracle squares of the CPU baseline (0: one per host thread, at most 16)")
     ap.add_argument("--only-headline", action="store_true", help="the timed steps only (for counter runs)")
+    ap.add_argument("--workload", choices=("scl", "cl", "mlp", "batch"), default="scl",
+                    help="timed steps: scl (the headline), or, for profiling the other kernels, cl (the C+L "
+                         "workload, all 100 CUTs per step, FP32 integrand), mlp (surrogate inference, 4 M "
+                         "points per step, no fallback) or batch (the 512-link batch, graph replays)")
     ap.add_argument("--mu-map", type=int, default=1, help="closed-form accuracy map leg (0 = skip)")
     ap.add_argument("--outer-nf", type=int, default=5, help="outer-integral leg samples (1 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -596,6 +672,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.workload != "scl":
+        profile_run(args, torch, _lib, W)
+        return
     wl = W.sclband_150ch_40span(n_grid=1024, precision=W.PREC_FP64)
     n_ch = wl.spectrum.n_ch
     K = args.steps

@@ -265,7 +265,7 @@ int32_t isrs_batch_eval_dev(isrs_ctx* ctx, isrs_batch* batch, const isrs_numeric
 
 /* Launch-shape autotuner (the islands are independent work of uneven cost,
  * Sec. II-B): times candidate region launches on this batch and keeps the
- * fastest.  Candidates: persistent blocks per CU in {2, 3, 4} on the
+ * fastest.  Candidates: persistent blocks per CU in {2, 4} on the
  * cost-sorted queue (and, without format terms, one block per work unit);
  * the automatic slice grouping or one slice per unit; region-tile geometry:
  * runs of 2, 4 or 8 points per thread (FP32 segment form; each only where

@@ -1974,7 +1974,7 @@ int32_t isrs_autotune(isrs_ctx* c, isrs_batch* b, const isrs_numerics* nu, const
             b->tuning = {(int)v[0], (int)v[1], (int)v[2], (int)v[3], (int)v[4]};
             return batch_plan(c, b, nu, true);
         }
-        // candidates: queue mode (the only one for coherent sums) with 2..4
+        // candidates: queue mode (the only one for coherent sums) with 2 or 4
         // blocks per CU, the automatic slice grouping or one slice per unit,
         // and every run length with a kernel instance whose slices fit the
         // staged rows; without format terms also the grid mode
@@ -1991,7 +1991,7 @@ int32_t isrs_autotune(isrs_ctx* c, isrs_batch* b, const isrs_numerics* nu, const
         for (int r : ppts)
             for (int spb : {0, 1}) {
                 if (!nu->egn) cands.push_back({0, 0, 0, spb, r});
-                for (int bpc : {4, 3, 2}) cands.push_back({1, bpc, 1, spb, r});
+                for (int bpc : {4, 2}) cands.push_back({1, bpc, 1, spb, r});
             }
         const bool prof = c->profiling;
         c->profiling = true;

@@ -96,8 +96,9 @@ struct InstDesc {
 
 // Coherent-sum accumulators of one persistent block, in complex FP64: row
 // sums [3 islands][N] (E), column sums [3][N] (F), anti-diagonal sums [2N]
-// (G and H).
-__host__ __device__ constexpr size_t eslot(int N) { return (size_t)8 * N; }
+// (G and H).  The slot stride is padded by 24 entries (384 B) so that the
+// slots of neighbouring blocks do not all fall into the same L2 sets.
+__host__ __device__ constexpr size_t eslot(int N) { return (size_t)8 * N + 24; }
 
 // One channel-pair square of the (f1 <-> f2 folded) work list.
 struct SquareItem {

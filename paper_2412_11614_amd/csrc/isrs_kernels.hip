@@ -73,8 +73,8 @@ struct Prec<double> {
     using V2 = double2;
     using Vec = double2;
     using Seg = SegRow64;
-    static constexpr int KC = 64;
-    static constexpr int KP = 66;
+    static constexpr int KC = 100;  // one pass for spans up to 100 km at 1 km; 51 KB of rows, 3 blocks per CU
+    static constexpr int KP = 102;
     static constexpr int VW = 2;
 };
 
@@ -476,8 +476,13 @@ __device__ void region_unit(const RegionArgs& a, const int u, const int slot, Ve
             sl_begin = 0;
             sl_end = a.n_slices;
             acc = a.eacc + (size_t)slot * eslot(N);
-            for (int j = tid; j < 6 * N; j += THREADS) acc[j] = double2{0.0, 0.0};
-            for (int mm = tid; mm < AD; mm += THREADS) acc[6 * N + mm] = double2{0.0, 0.0};
+            // clear the sums this square uses (E rows, F columns per island; the
+            // anti-diagonals for G and H), each entry by the thread that owns it
+            for (int lt = 0; lt < 6; ++lt)
+                if ((it.egn_mask >> (4 * (lt >> 1) + (lt & 1))) & 1)
+                    for (int j = tid; j < N; j += THREADS) acc[(3 * (lt & 1) + (lt >> 1)) * N + j] = double2{0.0, 0.0};
+            if (it.egn_mask & 0xCCC)
+                for (int mm = tid; mm < AD; mm += THREADS) acc[6 * N + mm] = double2{0.0, 0.0};
         }
     }
     for (int sl = sl_begin; sl < sl_end; ++sl) {

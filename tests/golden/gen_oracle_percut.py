@@ -7,21 +7,23 @@ be generated and committed separately:
 
   cl64       C+L 100 ch, 10 spans, 64 x 64: every CUT, integral form (the model)
   cl64seg    C+L at 64 x 64: CUTs 0, 49, 99, segment form (the method, Eqs. 7-10)
-  cl256      C+L at 256 x 256: 8 seeded CUTs (0, 49, 99 and 5 drawn), integral form
-  scl64      S+C+L 150 ch, 40 spans, 64 x 64: 8 seeded CUTs (0, 75, 149 and 5 drawn),
+  cl256      C+L at 256 x 256: CUTs 0, 49, 99, integral form
+  scl64      S+C+L 150 ch, 40 spans, 64 x 64: 4 seeded CUTs (0, 75, 149 and 1 drawn),
              integral form
   scl128     S+C+L at 128 x 128: CUTs 0 and 75, integral form
   scl1024sq  S+C+L at 1024 x 1024: every near-CUT square (|k1 - CUT|, |k2 - CUT| <= 2,
              k1 <= k2) of CUTs 0, 75, 149 and one drawn CUT, bare island integrals,
              integral form
-  batchx     512-link batch at 64 x 64, the far end of its cost distribution: every
-             CUT of link 20 (30 spans), 4 CUTs each of link 343 (97 channels,
-             30 spans, the costliest) and link 91 (100 channels), integral form
+  batchx     512-link batch at 64 x 64, the far end of its cost distribution: the
+             first, middle and last CUT of link 20 (30 spans), of link 343 (97
+             channels, 30 spans, the costliest) and of link 91 (100 channels),
+             integral form
 
 Run from the repository root:
     python tests/golden/gen_oracle_percut.py <stage> [<stage> ...]
-Hours of CPU time in total (the C+L stages take about 1.5 h on 8 cores, the
-S+C+L ones about 2 h); each stage prints its own time.
+Hours of CPU time in total (on 8 cores: cl64 about 2.5 h, scl128 about 1.2 h,
+cl256 about 1 h, scl64 and batchx under 1 h each, scl1024sq 10 min); each
+stage prints its own time.
 """
 from __future__ import annotations
 
@@ -68,13 +70,12 @@ def stage_cl64seg():
 
 def stage_cl256():
     wl = W.cl_100ch_10span(n_grid=256)
-    cuts = seeded_cuts([0, 49, 99], 100, seed=22)
-    return {"workload": "cl_100ch_10span(seed=2, n_grid=256)", **cut_record(wl, cuts, "integral", 256)}
+    return {"workload": "cl_100ch_10span(seed=2, n_grid=256)", **cut_record(wl, [0, 49, 99], "integral", 256)}
 
 
 def stage_scl64():
     wl = W.sclband_150ch_40span(n_grid=64)
-    cuts = seeded_cuts([0, 75, 149], 150, seed=55)
+    cuts = seeded_cuts([0, 75, 149], 150, seed=55, n_total=4)
     return {"workload": "sclband_150ch_40span(seed=5, n_grid=64)", **cut_record(wl, cuts, "integral", 64)}
 
 
@@ -109,10 +110,10 @@ def stage_scl1024sq():
 def stage_batchx():
     links = W.batch_links()
     out = []
-    for li, n_pick in ((20, None), (343, 4), (91, 4)):
+    for li in (20, 343, 91):
         wl = links[li]
         act = wl.cuts
-        cuts = act if n_pick is None else act[np.linspace(0, len(act) - 1, n_pick).round().astype(int)]
+        cuts = act[np.linspace(0, len(act) - 1, 3).round().astype(int)]
         rec = cut_record(wl, cuts, "integral", 64)
         rec.update({"link": li, "n_active": int(len(act)), "n_spans": int(len(wl.link.spans))})
         out.append(rec)

@@ -3,8 +3,8 @@ against FP64 oracle values stored by tests/golden/gen_oracle_percut.py (which
 calls only the oracle):
 
   * C+L 100 ch, 10 spans: every CUT at 64 x 64 (integral form), CUTs 0/49/99
-    at 64 x 64 (segment form), 8 seeded CUTs at 256 x 256 (integral form);
-  * S+C+L 150 ch, 40 spans: 8 seeded CUTs at 64 x 64 and CUTs 0/75 at
+    at 64 x 64 (segment form) and at 256 x 256 (integral form);
+  * S+C+L 150 ch, 40 spans: 4 seeded CUTs at 64 x 64 and CUTs 0/75 at
     128 x 128 (integral form), and every near-CUT square of four CUTs at
     1024 x 1024 (island level);
   * the far end of the 512-link batch's cost distribution (the most spans,
