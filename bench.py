@@ -328,7 +328,7 @@ def per_cut_dz_leg(eng, wl, eta_dz1, W, torch):
             "max_abs_db_vs_dz1": float(np.max(np.abs(10 * np.log10(r["eta"] / eta_dz1))))}
 
 
-def surrogate_leg(eng, n_points, torch, train_rows=1 << 22, members=4):
+def surrogate_leg(eng, n_points, torch, train_rows=1 << 22, members=4, heldout_links=1024, loop_links=8):
     """Ensemble surrogate of the per-span FWM factor: training time, held-out
     error against the closed form, and throughput of inference with fallback
     (0.01 dB spread threshold) against the closed form on the same points."""
@@ -400,7 +400,8 @@ def surrogate_leg(eng, n_points, torch, train_rows=1 << 22, members=4):
         loop[name] = {"s": dt, "fallback_fraction": fb,
                       "eta_err_db": [float(v) for v in 10 * np.log10(eta / ref)]}
     s.close()
-    link_trained = surrogate_link_leg(eng, torch, W, train_rows, members, wl, cuts, ref)
+    link_trained = surrogate_link_leg(eng, torch, W, train_rows, members, wl, cuts, ref,
+                                      heldout_links=heldout_links, loop_links=loop_links)
     return {"workload": (f"{members}-member 16-256x4-1 SiLU ensemble, BF16 MFMA; trained on {train_rows} "
                          f"closed-form samples (2000 Adam steps of 1024 per member); {n_points} query points "
                          f"(100 x 100 GHz grid squares, 80-100 km spans, 17-23 dBm)"),
@@ -412,16 +413,19 @@ def surrogate_leg(eng, n_points, torch, train_rows=1 << 22, members=4):
             "eta_in_the_loop": loop, "link_trained": link_trained}
 
 
-def surrogate_link_leg(eng, torch, W, train_rows, members, wl, cuts, ref, n_links=64):
-    """The same ensemble trained on the query distribution of real links: points
+def surrogate_link_leg(eng, torch, W, train_rows, members, wl, cuts, ref, n_links=64, heldout_links=1024,
+                       heldout_points=4096, loop_links=8):
+    """The ensemble trained on the query distribution of real links: points
     drawn from the CUTs, channel pairs, grid cells and spans of n_links C+L
-    links (the benchmark link's distribution, seeds 100..), tested on points of
-    n_links held-out links (seeds 1000..) and in the loop on the benchmark link
-    (seed 2)."""
+    links (the benchmark link's distribution, seeds 100..), its fallback gate
+    calibrated on points of n_links other links (seeds 500..) to 0.007 dB per
+    point, then tested on heldout_points points of each of heldout_links
+    held-out links (seeds 1000..) and in the loop on loop_links links (seeds
+    2000..; CUTs 3, 50, 96 at 64 x 64)."""
     db = 10.0 / np.log(10.0)
 
-    def draw(seed0, n, seed):
-        b = eng.batch([W.cl_100ch_10span(seed=seed0 + i, n_grid=wl.numerics.n_grid) for i in range(n_links)])
+    def draw(seed0, n_l, n, seed):
+        b = eng.batch([W.cl_100ch_10span(seed=seed0 + i, n_grid=wl.numerics.n_grid) for i in range(n_l)])
         x = torch.empty(n, 16, device="cuda")
         r = torch.empty(n, device="cuda")
         rej = eng.surrogate_datagen_batch(b, wl.numerics.n_grid, x, r, seed)
@@ -429,37 +433,77 @@ def surrogate_link_leg(eng, torch, W, train_rows, members, wl, cuts, ref, n_link
         return x, r, rej
 
     t0 = time.perf_counter()
-    x, r, rej = draw(100, train_rows, 4)
+    x, r, rej = draw(100, n_links, train_rows, 4)
     t_gen = time.perf_counter() - t0
     s = eng.surrogate(members, seed=5)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    s.train(x, r, steps=1500, batch=1024, lr=1e-3)
-    loss = s.train(x, r, steps=500, batch=1024, lr=3e-4)
+    s.train(x, r, steps=4000, batch=1024, lr=1e-3)
+    s.train(x, r, steps=2000, batch=1024, lr=3e-4)
+    loss = s.train(x, r, steps=2000, batch=1024, lr=1e-4)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     del x, r
-    xh, _, _ = draw(1000, 8192, 1000)
-    ycf = torch.empty(8192, device="cuda")
+    xc, _, _ = draw(500, n_links, 1 << 20, 5)
+    thr, cal_err, cal_frac = s.calibrate(xc, 0.007)
+    del xc
+    # held-out points: errors without fallback, at the calibrated gate, and the spread -> error map
+    nh = heldout_links * heldout_points
+    t0 = time.perf_counter()
+    xh, _, _ = draw(1000, heldout_links, nh, 1000)
+    t_hgen = time.perf_counter() - t0
+    ycf = torch.empty(nh, device="cuda")
     eng.closed_form_points(xh, ycf)
-    yh = torch.empty(8192, device="cuda")
+    mean = torch.empty(nh, device="cuda")
+    spread = torch.empty(nh, device="cuda")
+    s.predict(xh, mean, spread)
+    yh = torch.empty(nh, device="cuda")
     held = {}
-    for thr in (float("inf"), 0.01):
-        nf = s.eval_points(xh, yh, thr)
-        err = db * (yh - ycf).double().cpu().numpy()
-        held["no_fallback" if thr == float("inf") else "thr_0p01_db"] = {
-            "rms_db": float(np.sqrt(np.mean(err ** 2))), "max_abs_db": float(np.abs(err).max()),
-            "fallback_fraction": nf / 8192}
-    eng.load(wl)
-    loop = {}
-    for name, thr in (("no_fallback", float("inf")), ("thr_0p01_db", 0.01)):
-        eta, fb = s.eval_eta(wl.numerics, cuts, thr)
-        loop[name] = {"fallback_fraction": fb, "eta_err_db": [float(v) for v in 10 * np.log10(eta / ref)]}
+    for name, t in (("no_fallback", float("inf")), ("calibrated_gate", thr)):
+        nf = s.eval_points(xh, yh, t)
+        err = np.abs(db * (yh - ycf).double().cpu().numpy())
+        held[name] = {"rms_db": float(np.sqrt(np.mean(err ** 2))), "max_abs_db": float(err.max()),
+                      "fallback_fraction": nf / nh}
+    s.eval_points(xh, yh, float("inf"))
+    err = np.abs(db * (yh - ycf).double().cpu().numpy())
+    spr = db * spread.double().cpu().numpy()
+    qs = np.quantile(spr, np.linspace(0, 1, 11))
+    smap = []
+    for lo, hi in zip(qs[:-1], qs[1:]):
+        m = (spr >= lo) & (spr <= hi)
+        smap.append({"spread_db": [float(lo), float(hi)], "max_err_db": float(err[m].max()),
+                     "p99_err_db": float(np.quantile(err[m], 0.99))})
+    del xh, ycf, mean, spread, yh
+    # in the loop
+    loop_cuts = np.array([3, 50, 96], dtype=np.int32)
+    loop = {"links": loop_links, "cuts": loop_cuts.tolist(), "max_abs_db_no_fallback": 0.0,
+            "max_abs_db_calibrated_gate": 0.0, "fallback_fraction": [], "s_surrogate": 0.0, "s_closed_form": 0.0}
+    for i in range(loop_links):
+        w = W.cl_100ch_10span(seed=2000 + i, n_grid=64)
+        eng.load(w)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ref_i = eng.eval_eta(w.numerics, loop_cuts, precision=W.PREC_FP32_PHASE64)["eta"]
+        loop["s_closed_form"] += time.perf_counter() - t0
+        eta_n, _ = s.eval_eta(w.numerics, loop_cuts, float("inf"))
+        t0 = time.perf_counter()
+        eta_g, fb = s.eval_eta(w.numerics, loop_cuts, thr)
+        loop["s_surrogate"] += time.perf_counter() - t0
+        loop["max_abs_db_no_fallback"] = max(loop["max_abs_db_no_fallback"],
+                                             float(np.max(np.abs(10 * np.log10(eta_n / ref_i)))))
+        loop["max_abs_db_calibrated_gate"] = max(loop["max_abs_db_calibrated_gate"],
+                                                 float(np.max(np.abs(10 * np.log10(eta_g / ref_i)))))
+        loop["fallback_fraction"].append(fb)
     s.close()
-    return {"workload": (f"{train_rows} points from {n_links} C+L links (seeds 100-{99 + n_links}), "
-                         f"held-out points from {n_links} others (seeds 1000-{999 + n_links})"),
-            "datagen_s": t_gen, "rejected_draws": rej, "train_s": t_train,
-            "train_loss_ln2": [float(v) for v in loss], "held_out_8192": held, "eta_in_the_loop": loop}
+    return {"workload": (f"{train_rows} points from {n_links} C+L links (seeds 100-{99 + n_links}), gate calibrated on "
+                         f"1048576 points of {n_links} others (seeds 500-), {heldout_points} held-out points on each of "
+                         f"{heldout_links} links (seeds 1000-), in the loop on {loop_links} links (seeds 2000-)"),
+            "datagen_s": t_gen, "rejected_draws": rej, "train_s": t_train, "train_steps_per_member": 8000,
+            "train_loss_ln2": [float(v) for v in loss],
+            "gate": {"target_db": 0.007, "threshold_db": thr, "calibration_max_err_db": cal_err,
+                     "calibration_accepted": cal_frac},
+            "held_out": held, "held_out_points": nh, "held_out_datagen_s": t_hgen, "spread_to_error_map": smap,
+            "eta_in_the_loop": loop}
 
 
 def _gold(stage):
@@ -657,6 +701,10 @@ def main():
                     help="CUTs of the integral-form comparison leg (0 = skip)")
     ap.add_argument("--surrogate-points", type=int, default=1 << 22,
                     help="query points of the surrogate leg (0 = skip)")
+    ap.add_argument("--surrogate-heldout-links", type=int, default=1024,
+                    help="held-out links of the link-trained surrogate, 4096 points each (8192 at full scale)")
+    ap.add_argument("--surrogate-loop-links", type=int, default=8,
+                    help="links of the surrogate-in-the-loop test, 3 CUTs each (256 at full scale)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the steps, copy this many MiB device-to-device (counter calibration)")
     args = ap.parse_args()
@@ -700,6 +748,7 @@ def main():
     t0 = time.perf_counter()
     for i, cut in enumerate(step_cuts):
         step(i, cut)
+        log(f"step {i} (CUT {cut}) queued at {time.perf_counter() - t0:.1f} s")   # the host runs a step ahead
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     log(f"timed: {K} CUTs in {elapsed:.2f} s")
@@ -774,7 +823,8 @@ def main():
             out["batched"] = batched_leg(eng, args.batch_links, args.plain_links, W, torch)
         if args.surrogate_points > 0:
             log("surrogate leg")
-            out["surrogate"] = surrogate_leg(eng, args.surrogate_points, torch)
+            out["surrogate"] = surrogate_leg(eng, args.surrogate_points, torch, heldout_links=args.surrogate_heldout_links,
+                                         loop_links=args.surrogate_loop_links)
     eng.close()
 
     if args.calib_copy_mib:

@@ -369,6 +369,20 @@ int32_t isrs_surrogate_predict(isrs_ctx* ctx, isrs_surrogate* sur, const float* 
 int32_t isrs_surrogate_eval_points(isrs_ctx* ctx, isrs_surrogate* sur, const float* x_dev, int64_t n,
                                    double spread_db_threshold, float* y_dev, int64_t* n_fallback);
 
+/* Calibrates the fallback gate on n labelled query points x_dev (device
+ * [n*16], e.g. from isrs_surrogate_datagen_batch): each point's error is the
+ * ensemble mean against the closed form (FP64, Eqs. 7-10), in dB of
+ * |mu|^2, and the spread the gate compares.  threshold_db (host) receives
+ * the largest spread threshold for which every calibration point the gate
+ * accepts (spread <= threshold) is within target_db of the closed form, or
+ * -1 when none is (all points then fall back); max_err_db and
+ * accepted_fraction (host, nullable) receive the largest accepted error and
+ * the accepted share.  Synchronises the context's stream.  The ensemble's
+ * spread is not an error bound by itself; this call measures the map from
+ * one to the other on data of the intended query distribution. */
+int32_t isrs_surrogate_calibrate(isrs_ctx* ctx, isrs_surrogate* sur, const float* x_dev, int64_t n, double target_db,
+                                 double* threshold_db, double* max_err_db, double* accepted_fraction);
+
 /* Closed form only, same query points and output as above. */
 int32_t isrs_closed_form_points(isrs_ctx* ctx, const float* x_dev, int64_t n, float* y_dev);
 

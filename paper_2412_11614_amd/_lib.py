@@ -40,7 +40,7 @@ EXPORTED = [
     "isrs_surrogate_num_params", "isrs_surrogate_get_params", "isrs_surrogate_set_params",
     "isrs_surrogate_grad", "isrs_surrogate_save", "isrs_surrogate_load", "isrs_surrogate_get_target_scale",
     "isrs_eval_eta_surrogate", "isrs_eval_eta_dz", "isrs_choose_dz", "isrs_surrogate_datagen_batch",
-    "isrs_eval_eta_dev_noalloc",
+    "isrs_eval_eta_dev_noalloc", "isrs_surrogate_calibrate",
 ]
 
 SUR_FEATURES = 16
@@ -141,6 +141,7 @@ def lib():
     L.isrs_surrogate_predict.argtypes = [vp, vp, vp, C.c_int64, vp, vp]
     L.isrs_surrogate_eval_points.argtypes = [vp, vp, vp, C.c_int64, C.c_double, vp, C.POINTER(C.c_int64)]
     L.isrs_closed_form_points.argtypes = [vp, vp, C.c_int64, vp]
+    L.isrs_surrogate_calibrate.argtypes = [vp, vp, vp, C.c_int64, C.c_double, dp, dp, dp]
     L.isrs_surrogate_num_params.argtypes = [C.POINTER(C.c_int64)]
     L.isrs_surrogate_get_params.argtypes = [vp, C.c_int32, fp]
     L.isrs_surrogate_set_params.argtypes = [vp, vp, C.c_int32, fp]
@@ -369,6 +370,15 @@ class Surrogate:
             self._e._h, self._h, _dev(x, "torch.float32", 16 * n), n, float(spread_db_threshold),
             _dev(y, "torch.float32", n), C.byref(nf)))
         return int(nf.value)
+
+    def calibrate(self, x, target_db):
+        """Fallback threshold from labelled points x: returns (threshold_db,
+        max accepted error dB, accepted fraction)."""
+        n = x.numel() // SUR_FEATURES
+        t, e, f = C.c_double(), C.c_double(), C.c_double()
+        self._e._check(self._e._L.isrs_surrogate_calibrate(self._e._h, self._h, _dev(x, "torch.float32", 16 * n), n,
+                                                           float(target_db), C.byref(t), C.byref(e), C.byref(f)))
+        return t.value, e.value, f.value
 
     def get_params(self, member):
         p = np.zeros(self.n_params, dtype=np.float32)

@@ -21,6 +21,7 @@
 #include <cstring>
 #include <fstream>
 #include <new>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -817,6 +818,8 @@ struct isrs_surrogate {
     int* off = nullptr;
     int* total = nullptr;
     int64_t* idx = nullptr;
+    float* cal = nullptr;             // calibration: mean, spread, reference [3 x ccap]
+    int64_t ccap = 0;
     int64_t fcap = 0;
     // query rows of the table path
     float* qx = nullptr;
@@ -1174,6 +1177,7 @@ int32_t isrs_surrogate_destroy(isrs_surrogate* s)
         dfree(s->off);
         dfree(s->total);
         dfree(s->idx);
+        dfree(s->cal);
         dfree(s->qx);
         dfree(s->qstate);
         dfree(s->qcnt);
@@ -1428,6 +1432,62 @@ int32_t isrs_surrogate_eval_points(isrs_ctx* c, isrs_surrogate* s, const float* 
             S_TRY(c, hipStreamSynchronize(st));
             *n_fallback = t;
         }
+        return ISRS_OK;
+    } catch (...) {
+        return abi_exception(c);
+    }
+}
+
+int32_t isrs_surrogate_calibrate(isrs_ctx* c, isrs_surrogate* s, const float* x, int64_t n, double target_db,
+                                 double* threshold_db, double* max_err_db, double* accepted_fraction)
+{
+    try {
+        if (!c) return ISRS_E_ARG;
+        if (!s || !x || !threshold_db || n < 1 || n > (int64_t)1 << 31)
+            return ctx_fail(c, ISRS_E_ARG, "null argument or bad n");
+        if (!(target_db > 0) || !std::isfinite(target_db)) return ctx_fail(c, ISRS_E_ARG, "target must be > 0");
+        S_TRY(c, hipSetDevice(s->device));
+        hipStream_t st = ctx_stream(c);
+        int32_t rc = predict_members(c, s, x, n, st);
+        if (rc) return rc;
+        if (n > s->ccap) {
+            release(s->cal);
+            s->ccap = 0;
+            S_TRY(c, dalloc(&s->cal, (size_t)n * 3));
+            s->ccap = n;
+        }
+        float* mean = s->cal;
+        float* spread = s->cal + n;
+        float* ref = s->cal + 2 * n;
+        hipLaunchKernelGGL(ensemble_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, s->n_members, s->pred, x, mean,
+                           spread, nullptr, 0.0, nullptr);
+        hipLaunchKernelGGL(label_kernel, dim3(blocks_for(n, 128)), dim3(128), 0, st, n, x, ref, nullptr);
+        S_TRY(c, hipGetLastError());
+        std::vector<float> h((size_t)n * 3);
+        S_TRY(c, hipMemcpyAsync(h.data(), s->cal, h.size() * sizeof(float), hipMemcpyDeviceToHost, st));
+        S_TRY(c, hipStreamSynchronize(st));
+        // errors and spreads in dB of |mu|^2; accept points in order of spread
+        // while the largest error so far stays within the target, and stop only
+        // between distinct spreads (the gate accepts spread <= threshold)
+        const double db = 10.0 / std::log(10.0);
+        std::vector<int64_t> order((size_t)n);
+        std::iota(order.begin(), order.end(), 0);
+        std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return h[n + a] < h[n + b]; });
+        double run = 0.0, best_err = 0.0;
+        int64_t best = 0;
+        for (int64_t k = 0; k < n; ++k) {
+            const int64_t i = order[k];
+            const double e = std::fabs((double)h[i] - (double)h[2 * n + i]) * db;
+            if (!(e <= target_db) || std::isnan(e)) break;
+            run = std::max(run, e);
+            if (k + 1 == n || h[n + order[k + 1]] > h[n + i]) {
+                best = k + 1;
+                best_err = run;
+            }
+        }
+        *threshold_db = best > 0 ? (double)h[n + order[best - 1]] * db : -1.0;
+        if (max_err_db) *max_err_db = best_err;
+        if (accepted_fraction) *accepted_fraction = (double)best / (double)n;
         return ISRS_OK;
     } catch (...) {
         return abi_exception(c);
