@@ -452,6 +452,7 @@ def surrogate_link_leg(eng, torch, W, train_rows, members, wl, cuts, ref, n_link
     t0 = time.perf_counter()
     xh, _, _ = draw(1000, heldout_links, nh, 1000)
     t_hgen = time.perf_counter() - t0
+    log(f"surrogate: {nh} held-out points from {heldout_links} links drawn in {t_hgen:.1f} s")
     ycf = torch.empty(nh, device="cuda")
     eng.closed_form_points(xh, ycf)
     mean = torch.empty(nh, device="cuda")
@@ -494,6 +495,8 @@ def surrogate_link_leg(eng, torch, W, train_rows, members, wl, cuts, ref, n_link
         loop["max_abs_db_calibrated_gate"] = max(loop["max_abs_db_calibrated_gate"],
                                                  float(np.max(np.abs(10 * np.log10(eta_g / ref_i)))))
         loop["fallback_fraction"].append(fb)
+        if (i + 1) % 32 == 0:
+            log(f"surrogate in the loop: {i + 1} of {loop_links} links")
     s.close()
     return {"workload": (f"{train_rows} points from {n_links} C+L links (seeds 100-{99 + n_links}), gate calibrated on "
                          f"1048576 points of {n_links} others (seeds 500-), {heldout_points} held-out points on each of "
