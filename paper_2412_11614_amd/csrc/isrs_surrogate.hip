@@ -339,12 +339,18 @@ __global__ void features_kernel(int rows, const float* x, __bf16* xb)
     for (int j = 0; j < NIN; ++j) xb[(long)i * NIN + j] = (__bf16)f[j];
 }
 
-// Fused inference: a block takes FB_M query points through every member's
-// four hidden layers and output layer.  The activations of the tile stay in
-// LDS (BF16, rows padded to LDH so the 16-byte row reads of an MFMA operand
-// fall in distinct banks); weights stream from L2 as W^T rows.  Wave w owns
-// output columns 64 w .. 64 w + 63 of every layer: 4 x 2 tiles of 32 x 32.
-constexpr int FB_M = 128;
+// Fused inference: a block takes FB_RT * 32 query points through every
+// member's four hidden layers and output layer.  The activations of the tile
+// stay in LDS (BF16, rows padded to LDH so the 16-byte row reads of an MFMA
+// operand fall in distinct banks); weights stream from L2 as W^T rows.  Wave w
+// owns output columns 64 w .. 64 w + 63 of every layer: FB_RT x 2 tiles of
+// 32 x 32.  Two blocks share a CU.  (8 row tiles, 256 points per block,
+// halves the weight reads per point but leaves one wave per SIMD, its 256
+// accumulators in the accumulation registers: 15% slower, the operand loads
+// then wait with no other wave to switch to.)
+constexpr int FB_RT = 4;
+constexpr int FB_M = 32 * FB_RT;
+constexpr int FB_MINB = FB_RT > 4 ? 1 : 2;   // resident blocks per CU the registers are budgeted for
 constexpr int LDH = NH + 8;
 constexpr int LDX = NIN + 8;
 
@@ -354,12 +360,12 @@ constexpr int LDX = NIN + 8;
 // from L2); B operand: activation rows of the tile (16 bytes along k, LDS).
 template <int K, int LD>
 __device__ __forceinline__ void fused_products(const __bf16* src, const __bf16* Wt, int w, int lr, int kh,
-                                               f16v (&acc)[2][4])
+                                               f16v (&acc)[2][FB_RT])
 {
 #pragma unroll
     for (int ft = 0; ft < 2; ++ft)
 #pragma unroll
-        for (int rt = 0; rt < 4; ++rt) acc[ft][rt] = f16v{};
+        for (int rt = 0; rt < FB_RT; ++rt) acc[ft][rt] = f16v{};
 #pragma unroll
     for (int ks = 0; ks < K / 16; ++ks) {
         const int kk = 16 * ks + kh;
@@ -367,7 +373,7 @@ __device__ __forceinline__ void fused_products(const __bf16* src, const __bf16* 
 #pragma unroll
         for (int ft = 0; ft < 2; ++ft) av[ft] = *reinterpret_cast<const bf8*>(Wt + (size_t)(64 * w + 32 * ft + lr) * K + kk);
 #pragma unroll
-        for (int rt = 0; rt < 4; ++rt) {
+        for (int rt = 0; rt < FB_RT; ++rt) {
             const bf8 bv = *reinterpret_cast<const bf8*>(src + (32 * rt + lr) * LD + kk);
 #pragma unroll
             for (int ft = 0; ft < 2; ++ft)
@@ -386,22 +392,22 @@ struct FusedArgs {
     const float* p[MAX_MEMBERS];        // FP32 parameters (biases, w5, b5)
 };
 
-__global__ void __launch_bounds__(256, 2) mlp_fused_kernel(FusedArgs a)
+__global__ void __launch_bounds__(256, FB_MINB) mlp_fused_kernel(FusedArgs a)
 {
     __shared__ __attribute__((aligned(16))) __bf16 Hs[FB_M * LDH];
     __shared__ __attribute__((aligned(16))) __bf16 Xs[FB_M * LDX];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int64_t row0 = (int64_t)blockIdx.x * FB_M;
-    if (tid < FB_M) {
+    for (int rr = tid; rr < FB_M; rr += 256) {
         float f[NIN];
-        if (row0 + tid < a.n) {
-            features_row(a.x + (row0 + tid) * NIN, f);
+        if (row0 + rr < a.n) {
+            features_row(a.x + (row0 + rr) * NIN, f);
         } else {
 #pragma unroll
             for (int j = 0; j < NIN; ++j) f[j] = 0.0f;
         }
 #pragma unroll
-        for (int j = 0; j < NIN; ++j) Xs[tid * LDX + j] = (__bf16)f[j];
+        for (int j = 0; j < NIN; ++j) Xs[rr * LDX + j] = (__bf16)f[j];
     }
     __syncthreads();
     const int lr = lane & 31, kh = 8 * (lane >> 5);
@@ -410,7 +416,7 @@ __global__ void __launch_bounds__(256, 2) mlp_fused_kernel(FusedArgs a)
         for (int l = 0; l < 4; ++l) {
             const __bf16* src = l == 0 ? Xs : Hs;
             const __bf16* Wt = a.wt[m][l];
-            f16v acc[2][4];
+            f16v acc[2][FB_RT];
             if (l == 0)
                 fused_products<NIN, LDX>(src, Wt, w, lr, kh, acc);
             else
@@ -427,7 +433,7 @@ __global__ void __launch_bounds__(256, 2) mlp_fused_kernel(FusedArgs a)
                     const float4 bq = *reinterpret_cast<const float4*>(bias + f0);
                     const float bb[4] = {bq.x, bq.y, bq.z, bq.w};
 #pragma unroll
-                    for (int rt = 0; rt < 4; ++rt) {
+                    for (int rt = 0; rt < FB_RT; ++rt) {
                         bf4 hv;
 #pragma unroll
                         for (int e = 0; e < 4; ++e) {
@@ -439,16 +445,17 @@ __global__ void __launch_bounds__(256, 2) mlp_fused_kernel(FusedArgs a)
                 }
             __syncthreads();
         }
-        // output layer: two threads per row, 128 columns each
+        // output layer: 256 / FB_M threads per row, split over the columns
         {
-            const int rr = tid >> 1, half = tid & 1;
-            const float* w5 = pm + OFF_W5 + 128 * half;
-            const __bf16* h = Hs + rr * LDH + 128 * half;
+            constexpr int TPR = 256 / FB_M, CPT = NH / TPR;
+            const int rr = tid / TPR, part = tid % TPR;
+            const float* w5 = pm + OFF_W5 + CPT * part;
+            const __bf16* h = Hs + rr * LDH + CPT * part;
             float s = 0.0f;
 #pragma unroll 8
-            for (int c = 0; c < 128; ++c) s += (float)h[c] * w5[c];
-            s += __shfl_xor(s, 1, 64);
-            if (half == 0 && row0 + rr < a.n) a.pred[(int64_t)m * a.n + row0 + rr] = a.shift + a.scale * (s + pm[OFF_B5]);
+            for (int c = 0; c < CPT; ++c) s += (float)h[c] * w5[c];
+            if constexpr (TPR == 2) s += __shfl_xor(s, 1, 64);
+            if (part == 0 && row0 + rr < a.n) a.pred[(int64_t)m * a.n + row0 + rr] = a.shift + a.scale * (s + pm[OFF_B5]);
         }
         __syncthreads();  // the tile's activations are free for the next member
     }
