@@ -51,11 +51,17 @@ def seeded_cuts(fixed, n_ch, seed, n_total=8):
 
 
 def cut_record(wl, cuts, method, n_grid):
+    # one CUT per oracle call, each announced when done (long stages show progress)
     t0 = time.time()
-    r = oracle.eval_cuts(wl, cuts=cuts, method=method, n_grid=n_grid)
+    eta, s2, terms = [], [], []
+    for c in cuts:
+        r = oracle.eval_cuts(wl, cuts=[int(c)], method=method, n_grid=n_grid)
+        eta.append(float(r["eta"][0]))
+        s2.append(float(r["sigma2"][0]))
+        terms.append([float(v) for v in r["terms"][0]])
+        print(f"  CUT {int(c)}: eta {eta[-1]:.6e} after {time.time() - t0:.0f} s", flush=True)
     return {"cuts": [int(c) for c in cuts], "method": method, "n_grid": n_grid,
-            "eta": r["eta"].tolist(), "sigma2": r["sigma2"].tolist(), "terms": r["terms"].tolist(),
-            "seconds": time.time() - t0}
+            "eta": eta, "sigma2": s2, "terms": terms, "seconds": time.time() - t0}
 
 
 def stage_cl64():
