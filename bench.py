@@ -90,6 +90,15 @@ def kernel_roofline(st, peak, name, stem):
     return r
 
 
+def _plain(o):
+    """JSON form of numpy scalars and arrays left in a result."""
+    if isinstance(o, np.generic):
+        return o.item()
+    if isinstance(o, np.ndarray):
+        return o.tolist()
+    raise TypeError(f"not JSON serializable: {type(o).__name__}")
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -553,7 +562,7 @@ def headline_accuracy(eng, W):
                                         "max_abs_db_of_gn_sum": float(worst)}
         errs.append(worst)
     out["max_abs_db_vs_oracle"] = float(max(errs)) if errs else None
-    out["within_0p01_db"] = bool(errs) and max(errs) <= 0.01
+    out["within_0p01_db"] = bool(errs) and bool(max(errs) <= 0.01)
     return out
 
 
@@ -677,7 +686,7 @@ def profile_run(args, torch, _lib, W):
         dst.copy_(src)
         torch.cuda.synchronize()
         out["calib_copy_bytes"] = 4 * n
-    print(json.dumps(out), flush=True)
+    print(json.dumps(out, default=_plain), flush=True)
 
 
 def main():
@@ -842,7 +851,7 @@ def main():
     if not args.no_cpu_baseline and not args.only_headline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_squares)
-    print(json.dumps(out), flush=True)
+    print(json.dumps(out, default=_plain), flush=True)
 
 
 if __name__ == "__main__":
