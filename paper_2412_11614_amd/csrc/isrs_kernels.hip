@@ -85,35 +85,33 @@ __device__ __forceinline__ void sincos_rev(float t, float* s, float* c)
     *c = __builtin_amdgcn_cosf(t);
 }
 
-// Sine and cosine of 2 pi t for a phase t in revolutions (|t| <= 1 here), in
+// Sine and cosine of 2 pi t for a phase t in revolutions (0 <= t < 1 here), in
 // FP64: t = k/4 + r with k the nearest quarter turn, so |r| <= 1/8 exactly;
-// the Taylor series of sin and cos at x = 2 pi r (|x| <= pi/4) through x^17
-// and x^18 (the first omitted terms are below 1e-19), then a rotation by k
-// quarter turns.
+// then sin(2 pi r) = r S(r^2) and cos(2 pi r) = 1 + r^2 C(r^2) with minimax
+// polynomials on r^2 in [0, 1/64] (S of degree 6: relative error 3.3e-18; C of
+// degree 5: error 6.1e-17; gen_sincos_coeffs.py derives both and measures
+// 1.4e-16 absolute error after FP64 evaluation), and a rotation by k quarter
+// turns.
 __device__ __forceinline__ void sincos_rev(double t, double* s, double* c)
 {
     const double k = rint(4.0 * t);
-    const double x = (t - 0.25 * k) * 6.283185307179586476925286766559;
-    const double x2 = x * x;
-    double ps = 2.8114572543455206e-15;          // 1/17!
-    ps = fma(ps, x2, -7.6471637318198164e-13);   // 1/15!
-    ps = fma(ps, x2, 1.6059043836821613e-10);    // 1/13!
-    ps = fma(ps, x2, -2.5052108385441720e-08);   // 1/11!
-    ps = fma(ps, x2, 2.7557319223985893e-06);    // 1/9!
-    ps = fma(ps, x2, -1.9841269841269841e-04);   // 1/7!
-    ps = fma(ps, x2, 8.3333333333333333e-03);    // 1/5!
-    ps = fma(ps, x2, -1.6666666666666667e-01);   // 1/3!
-    const double sx = fma(x * x2, ps, x);
-    double pc = 1.5619206968586225e-16;          // 1/18!
-    pc = fma(pc, x2, -4.7794773323873853e-14);   // 1/16!
-    pc = fma(pc, x2, 1.1470745597729725e-11);    // 1/14!
-    pc = fma(pc, x2, -2.0876756987868099e-09);   // 1/12!
-    pc = fma(pc, x2, 2.7557319223985891e-07);    // 1/10!
-    pc = fma(pc, x2, -2.4801587301587302e-05);   // 1/8!
-    pc = fma(pc, x2, 1.3888888888888889e-03);    // 1/6!
-    pc = fma(pc, x2, -4.1666666666666667e-02);   // 1/4!
-    pc = fma(pc, x2, 0.5);                       // 1/2!
-    const double cx = fma(-x2, pc, 1.0);
+    const double r = fma(k, -0.25, t);
+    const double w = r * r;
+    double ps = 3.7807261726947012;
+    ps = fma(ps, w, -15.093797505265384);
+    ps = fma(ps, w, 42.058684902054765);
+    ps = fma(ps, w, -76.70585970331514);
+    ps = fma(ps, w, 81.60524927594452);
+    ps = fma(ps, w, -41.341702240399634);
+    ps = fma(ps, w, 6.283185307179586);
+    const double sx = r * ps;
+    double pc = 7.810359872623236;
+    pc = fma(pc, w, -26.424265208852088);
+    pc = fma(pc, w, 60.244620355035806);
+    pc = fma(pc, w, -85.45681709411303);
+    pc = fma(pc, w, 64.93939402238959);
+    pc = fma(pc, w, -19.739208802178485);
+    const double cx = fma(w, pc, 1.0);
     const int q = (int)k & 3;
     const double s1 = (q & 1) ? cx : sx, c1 = (q & 1) ? sx : cx;
     *s = (q & 2) ? -s1 : s1;
@@ -521,13 +519,15 @@ __device__ void region_unit(const RegionArgs& a, const int u, const int slot, Ve
             // rotation of the span's contribution: gamma Pi e^{i Theta_s} (Eq. 22)
             R gm = spc_r<R>(sc.gamma, sc.f_gamma);
             if (lk.gain_mode == 1) gm *= exp_fast(R(sc.pi_a - sc.pi_s * ssum + sc.pi_c * cabs));
+            // the segment form applies gamma Pi with 1 / |i chi - alpha|^2 below
+            const R gr = MU == MU_SEG ? R(1) : gm;
             R rr[PPT], ri[PPT];
 #pragma unroll
             for (int r = 0; r < PPT; ++r) {
                 R st, ct;
                 sincos_rev(frac_rev<R>(pa[r] * fth), &st, &ct);
-                rr[r] = gm * ct;
-                ri[r] = gm * st;
+                rr[r] = gr * ct;
+                ri[r] = gr * st;
             }
             if constexpr (MU == MU_MAC) {
                 // Maclaurin form, Eqs. 4-6
@@ -605,9 +605,8 @@ __device__ void region_unit(const RegionArgs& a, const int u, const int slot, Ve
                 sincos_rev(frac_rev<R>(tq), &sq, &cq);
                 const R al = spc_r<R>(sc.alpha, sc.f_alpha), ch = R(tq) * spc_r<R>(sc.wd, sc.f_wd);
                 const R em = spc_r<R>(sc.em, sc.f_em);
-                const R qr = em * cq;
                 qi[r] = em * sq;
-                tq2[r] = R(2) * qr;
+                tq2[r] = (R(2) * em) * cq;
                 if constexpr (MU == MU_INT) {
                     cr[r] = rr[r];
                     ci[r] = ri[r];
@@ -627,8 +626,8 @@ __device__ void region_unit(const RegionArgs& a, const int u, const int slot, Ve
                         mre[r][j] = tr;
                     }
                 } else {
-                    const R vr = qr - R(1), vi = qi[r];
-                    const R inv = recip(al * al + ch * ch);
+                    const R vr = fma(em, cq, R(-1)), vi = qi[r];
+                    const R inv = (MU == MU_SEG ? gm : R(1)) * recip(al * al + ch * ch);
                     const R i0r = (-al * vr + ch * vi) * inv;
                     const R i0i = (-ch * vr - al * vi) * inv;
                     cr[r] = rr[r] * i0r - ri[r] * i0i;
