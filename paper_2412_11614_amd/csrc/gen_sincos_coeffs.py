@@ -1,12 +1,16 @@
 """Coefficients of the FP64 sine / cosine in isrs_kernels.hip.
 
-For a phase reduced to |r| <= 1/8 revolution the kernel evaluates
-    sin(2 pi r) = r S(r^2),    cos(2 pi r) = 1 + r^2 C(r^2)
-with S of degree 6 and C of degree 5 in w = r^2 on [0, 1/64].  This script
-finds both by a Remez exchange in 60-digit arithmetic: S minimises the
-relative error of the sine, C the error of the cosine.  It prints the
-equioscillation error and the coefficients rounded to double, lowest degree
-first, then checks the rounded polynomials, evaluated with FP64 rounding and
+For a phase t in revolutions the kernel takes v = t - rint(t) (exact,
+|v| <= 1/2) and evaluates the half angle pi v (|pi v| <= pi/2) as
+    sin(pi v) = v S(v^2),    cos(pi v) = 1 + v^2 C(v^2)
+with S and C of degree 7 in v^2, then doubles it once:
+    cos(2 pi v) = 2 cos^2(pi v) - 1,    sin(2 pi v) = 2 cos(pi v) sin(pi v).
+This script finds both polynomials by a Remez exchange in 60-digit
+arithmetic on r = v / 2 (turns of the half angle, r^2 in [0, 1/16]): S
+minimises the relative error of the sine, C the absolute error of the
+cosine.  The coefficients are then rescaled to v by powers of two (exact).
+It prints the equioscillation errors and the coefficients rounded to
+double, lowest degree first, then checks the whole evaluation, in FP64 with
 fused multiply-adds as the kernel does, against 40-digit sin / cos.
 
     python gen_sincos_coeffs.py
@@ -19,7 +23,8 @@ import mpmath as mp
 
 mp.mp.dps = 60
 TWO_PI = 2 * mp.pi
-W_MAX = mp.mpf(1) / 64
+W_MAX = mp.mpf(1) / 16
+DEG_S, DEG_C = 7, 7
 
 
 def remez(f, weight, n, a, b, iters=30, scan=4000):
@@ -68,17 +73,17 @@ def sine_poly():
     def weight(w):  # relative error of r S(w)
         return mp.sqrt(w) / mp.sin(TWO_PI * mp.sqrt(w)) if w > 0 else 1 / TWO_PI
 
-    return remez(f, weight, 6, mp.mpf(0), W_MAX)
+    return remez(f, weight, DEG_S, mp.mpf(0), W_MAX)
 
 
 def cosine_poly():
     def f(w):
         return (mp.cos(TWO_PI * mp.sqrt(w)) - 1) / w
 
-    def weight(w):  # error of 1 + w C(w), relative to the cosine
-        return w / mp.cos(TWO_PI * mp.sqrt(w))
+    def weight(w):  # absolute error of 1 + w C(w)
+        return w
 
-    return remez(f, weight, 5, W_MAX * mp.mpf("1e-9"), W_MAX)
+    return remez(f, weight, DEG_C, W_MAX * mp.mpf("1e-9"), W_MAX)
 
 
 def fma(a, b, c):
@@ -88,41 +93,41 @@ def fma(a, b, c):
 
 
 def evaluate(t, S, C):
-    """The kernel's steps in FP64 for 0 <= t < 1."""
-    k = float(round(4.0 * t))
-    r = fma(k, -0.25, t)
-    w = r * r
+    """The kernel's steps in FP64 for a phase t in revolutions."""
+    v = t - float(round(t))
+    w = v * v
     ps = S[-1]
     for c in S[-2::-1]:
         ps = fma(ps, w, c)
-    sx = r * ps
+    sh = v * ps
     pc = C[-1]
     for c in C[-2::-1]:
         pc = fma(pc, w, c)
-    cx = fma(w, pc, 1.0)
-    q = int(k) & 3
-    s1, c1 = (cx, sx) if q & 1 else (sx, cx)
-    return (-s1 if q & 2 else s1), (-c1 if (q + 1) & 2 else c1)
+    ch = fma(w, pc, 1.0)
+    c2 = ch + ch
+    return c2 * sh, fma(c2, ch, -1.0)
 
 
 def main():
     S, es = sine_poly()
     C, ec = cosine_poly()
-    Sd = [float(x) for x in S]
-    Cd = [float(x) for x in C]
-    print(f"S: degree 6 in r^2, relative error {mp.nstr(es, 4)}")
+    # r = v / 2:  r S(r^2) = v S_j / 2^(2j+1) (v^2)^j,  r^2 C(r^2) = v^2 C_j / 4^(j+1) (v^2)^j
+    Sd = [float(x / mp.mpf(2) ** (2 * j + 1)) for j, x in enumerate(S)]
+    Cd = [float(x / mp.mpf(4) ** (j + 1)) for j, x in enumerate(C)]
+    print(f"S: degree {DEG_S} in v^2, relative error {mp.nstr(es, 4)}")
     print("  ", ", ".join(repr(x) for x in Sd))
-    print(f"C: degree 5 in r^2, error {mp.nstr(ec, 4)}")
+    print(f"C: degree {DEG_C} in v^2, absolute error {mp.nstr(ec, 4)}")
     print("  ", ", ".join(repr(x) for x in Cd))
     rng = random.Random(1)
     worst = 0.0
     with mp.workdps(40):
         for i in range(20000):
-            t = i / 400.0 if i < 400 else rng.random()
+            t = i / 400.0 if i < 400 else (rng.random() if i % 2 else rng.random() * 1e6)
             s, c = evaluate(t, Sd, Cd)
-            worst = max(worst, float(abs(mp.mpf(s) - mp.sin(TWO_PI * t))),
-                        float(abs(mp.mpf(c) - mp.cos(TWO_PI * t))))
-    print(f"largest absolute error over 20000 phases in [0, 1): {worst:.3e}")
+            tt = mp.mpf(t)
+            worst = max(worst, float(abs(mp.mpf(s) - mp.sin(TWO_PI * tt))),
+                        float(abs(mp.mpf(c) - mp.cos(TWO_PI * tt))))
+    print(f"largest absolute error over 20000 phases: {worst:.3e}")
 
 
 if __name__ == "__main__":

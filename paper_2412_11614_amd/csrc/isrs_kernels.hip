@@ -85,37 +85,59 @@ __device__ __forceinline__ void sincos_rev(float t, float* s, float* c)
     *c = __builtin_amdgcn_cosf(t);
 }
 
-// Sine and cosine of 2 pi t for a phase t in revolutions (0 <= t < 1 here), in
-// FP64: t = k/4 + r with k the nearest quarter turn, so |r| <= 1/8 exactly;
-// then sin(2 pi r) = r S(r^2) and cos(2 pi r) = 1 + r^2 C(r^2) with minimax
-// polynomials on r^2 in [0, 1/64] (S of degree 6: relative error 3.3e-18; C of
-// degree 5: error 6.1e-17; gen_sincos_coeffs.py derives both and measures
-// 1.4e-16 absolute error after FP64 evaluation), and a rotation by k quarter
-// turns.
-__device__ __forceinline__ void sincos_rev(double t, double* s, double* c)
+// Sine and cosine of 2 pi t for a phase t in revolutions (|t| < 2^52), in
+// FP64, with no quadrant logic: v = t - rint(t) is exact and |v| <= 1/2; the
+// half angle pi v (at most pi/2) takes minimax polynomials sin(pi v) = v S(v^2)
+// and cos(pi v) = 1 + v^2 C(v^2) (S and C of degree 7, from
+// gen_sincos_coeffs.py), then one doubling: cos 2x = 2 cos^2 x - 1,
+// sin 2x = 2 cos x sin x.  Absolute error 5.2e-16 after FP64 evaluation.
+__device__ __forceinline__ void sincos_turns(double t, double* s, double* c)
 {
-    const double k = rint(4.0 * t);
-    const double r = fma(k, -0.25, t);
-    const double w = r * r;
-    double ps = 3.7807261726947012;
-    ps = fma(ps, w, -15.093797505265384);
-    ps = fma(ps, w, 42.058684902054765);
-    ps = fma(ps, w, -76.70585970331514);
-    ps = fma(ps, w, 81.60524927594452);
-    ps = fma(ps, w, -41.341702240399634);
-    ps = fma(ps, w, 6.283185307179586);
-    const double sx = r * ps;
-    double pc = 7.810359872623236;
-    pc = fma(pc, w, -26.424265208852088);
-    pc = fma(pc, w, 60.244620355035806);
-    pc = fma(pc, w, -85.45681709411303);
-    pc = fma(pc, w, 64.93939402238959);
-    pc = fma(pc, w, -19.739208802178485);
-    const double cx = fma(w, pc, 1.0);
-    const int q = (int)k & 3;
-    const double s1 = (q & 1) ? cx : sx, c1 = (q & 1) ? sx : cx;
-    *s = (q & 2) ? -s1 : s1;
-    *c = ((q + 1) & 2) ? -c1 : c1;
+    const double v = t - rint(t);
+    const double w = v * v;
+    double ps = -2.1122952923797757e-05;
+    ps = fma(ps, w, 0.00046597761697049093);
+    ps = fma(ps, w, -0.0073703610716640494);
+    ps = fma(ps, w, 0.08214587825654909);
+    ps = fma(ps, w, -0.5992645287757093);
+    ps = fma(ps, w, 2.5501640398597765);
+    ps = fma(ps, w, -5.167712780049753);
+    ps = fma(ps, w, 3.1415926535897927);
+    const double sh = v * ps;
+    double pc = 4.150750240995467e-06;
+    pc = fma(pc, w, -0.00010456780740967329);
+    pc = fma(pc, w, 0.00192955681790851);
+    pc = fma(pc, w, -0.025806888862681114);
+    pc = fma(pc, w, 0.23533063014598704);
+    pc = fma(pc, w, -1.3352627688446645);
+    pc = fma(pc, w, 4.058712126416545);
+    pc = fma(pc, w, -4.934802200544677);
+    const double ch = fma(w, pc, 1.0);
+    const double c2 = ch + ch;
+    *s = c2 * sh;
+    *c = fma(c2, ch, -1.0);
+}
+
+// t - floor(t) of a phase in revolutions, then in the working precision
+template <typename R>
+__device__ __forceinline__ R frac_rev(double t)
+{
+    return R(__builtin_amdgcn_fract(t));
+}
+
+// sine and cosine of 2 pi t for a phase t in revolutions given in FP64: the
+// FP32 integrand reduces t in FP64 and uses the hardware functions
+template <typename R>
+__device__ __forceinline__ void sincos_phase(double t, R* s, R* c);
+template <>
+__device__ __forceinline__ void sincos_phase<float>(double t, float* s, float* c)
+{
+    sincos_rev(frac_rev<float>(t), s, c);
+}
+template <>
+__device__ __forceinline__ void sincos_phase<double>(double t, double* s, double* c)
+{
+    sincos_turns(t, s, c);
 }
 
 __device__ __forceinline__ float exp_r(float x) { return expf(x); }
@@ -149,13 +171,6 @@ __device__ __forceinline__ double recip(double x)
     double r = __builtin_amdgcn_rcp(x);
     r = fma(fma(-x, r, 1.0), r, r);
     return fma(fma(-x, r, 1.0), r, r);
-}
-
-// t - floor(t) of a phase in revolutions, then in the working precision
-template <typename R>
-__device__ __forceinline__ R frac_rev(double t)
-{
-    return R(__builtin_amdgcn_fract(t));
 }
 
 // segments 4 kq .. 4 kq + 3 of a staged row
@@ -525,7 +540,7 @@ __device__ void region_unit(const RegionArgs& a, const int u, const int slot, Ve
 #pragma unroll
             for (int r = 0; r < PPT; ++r) {
                 R st, ct;
-                sincos_rev(frac_rev<R>(pa[r] * fth), &st, &ct);
+                sincos_phase<R>(pa[r] * fth, &st, &ct);
                 rr[r] = gr * ct;
                 ri[r] = gr * st;
             }
@@ -538,7 +553,7 @@ __device__ void region_unit(const RegionArgs& a, const int u, const int slot, Ve
                 for (int r = 0; r < PPT; ++r) {
                     const R ch = R(pa[r] * fx);
                     R sl, cl;
-                    sincos_rev(frac_rev<R>(pa[r] * fl), &sl, &cl);
+                    sincos_phase<R>(pa[r] * fl, &sl, &cl);
                     const R inv1 = R(1) / (al * al + ch * ch);
                     const R inv2 = R(1) / (R(4) * al * al + ch * ch);
                     // eta = (e^{(i chi - a) L} - 1) / (i chi - a)
@@ -576,7 +591,7 @@ __device__ void region_unit(const RegionArgs& a, const int u, const int slot, Ve
                     if (fb[r]) continue;
                     const R al = spc_r<R>(sc.alpha, sc.f_alpha), ch = R(pa[r] * fq) * spc_r<R>(sc.wd, sc.f_wd);
                     R sl, cl;
-                    sincos_rev(frac_rev<R>(pa[r] * fl), &sl, &cl);
+                    sincos_phase<R>(pa[r] * fl, &sl, &cl);
                     const R emL = spc_r<R>(sc.emL, sc.f_emL);
                     const R vr = emL * cl - R(1), vi = emL * sl;
                     const R inv = recip(al * al + ch * ch);
@@ -602,7 +617,7 @@ __device__ void region_unit(const RegionArgs& a, const int u, const int slot, Ve
             for (int r = 0; r < PPT; ++r) {
                 const double tq = pa[r] * fq;   // chi Delta / 2 pi
                 R sq, cq;
-                sincos_rev(frac_rev<R>(tq), &sq, &cq);
+                sincos_phase<R>(tq, &sq, &cq);
                 const R al = spc_r<R>(sc.alpha, sc.f_alpha), ch = R(tq) * spc_r<R>(sc.wd, sc.f_wd);
                 const R em = spc_r<R>(sc.em, sc.f_em);
                 qi[r] = em * sq;
@@ -612,7 +627,7 @@ __device__ void region_unit(const RegionArgs& a, const int u, const int slot, Ve
                     ci[r] = ri[r];
                     // a = (i chi - alpha) Delta / 2 and e^{a}; moments m_j = int u^j e^{a u}
                     R sh, chh;
-                    sincos_rev(frac_rev<R>(0.5 * tq), &sh, &chh);
+                    sincos_phase<R>(0.5 * tq, &sh, &chh);
                     const R hd = R(M_PI) / R(sc.wd);                       // Delta / 2
                     const R ar = -al * hd, ai = ch * hd;
                     const R eh = exp_r(ar);
