@@ -532,7 +532,12 @@ __device__ void region_unit(const RegionArgs& a, const int u, const int slot, Ve
             const double fq = fma(ssum, sc.c3r, sc.c2r);
             // rotation of the span's contribution: gamma Pi e^{i Theta_s} (Eq. 22)
             R gm = spc_r<R>(sc.gamma, sc.f_gamma);
-            if (lk.gain_mode == 1) gm *= exp_fast(R(sc.pi_a - sc.pi_s * ssum + sc.pi_c * cabs));
+            if (lk.gain_mode == 1) {
+                // a real (block-uniform) branch: the empty asm keeps the
+                // compiler from evaluating the exponential for every link
+                asm volatile("" ::: "memory");
+                gm *= exp_fast(R(sc.pi_a - sc.pi_s * ssum + sc.pi_c * cabs));
+            }
             // the segment form applies gamma Pi with 1 / |i chi - alpha|^2 below
             const R gr = MU == MU_SEG ? R(1) : gm;
             R rr[PPT], ri[PPT];
@@ -755,8 +760,9 @@ __device__ void region_unit(const RegionArgs& a, const int u, const int slot, Ve
                         pi = wr * pi + wi * pr;
                         pr = tr;
                     }
-                    ur[r] += cr[r] * pr - ci[r] * pi;
-                    ui[r] += cr[r] * pi + ci[r] * pr;
+                    // accumulated as two fused steps each
+                    ur[r] = fma(cr[r], pr, fma(-ci[r], pi, ur[r]));
+                    ui[r] = fma(cr[r], pi, fma(ci[r], pr, ui[r]));
                 }
             }
         }
