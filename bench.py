@@ -41,6 +41,7 @@ GOLDEN = os.path.join(ROOT, "tests", "golden")
 PROFILES = os.path.join(ROOT, "profiles")
 HEADLINE_PROFILE = "region_queue_kernel_fp64_scl150ch_40span_1024"
 CL_PROFILE = "region_queue_kernel_fp32_cl100ch_10span_256"
+BATCH_PROFILE = "region_queue_kernel_fp32_batch512_64"
 
 
 def kernel_source_hash():
@@ -227,7 +228,11 @@ def batched_leg(eng, n_links, n_plain, W, torch, tune_links=32):
             "tflops": flop / max(1, st.region_launches) / per_launch_s / 1e12,
             "frac": flop / max(1, st.region_launches) / per_launch_s / 1e12 / PEAK_FP32_TFLOPS,
             "region_ms_eager": st.region_ms, "live_points": st.n_points_live,
-            "default_region_ms_eager": st_default.region_ms}
+            "default_region_ms_eager": st_default.region_ms,
+            # executed FMA rate and HBM bytes per launch from the committed counter
+            # summaries of this launch (absent once the kernel source has changed)
+            **{k: float(v) for k, v in profile_fields(BATCH_PROFILE).items()
+               if k in ("fma_flop_per_s_frac", "traffic_bytes_per_launch")}}
 
 
 def integral_form_leg(eng, wl, W, torch, n_cuts=10):
