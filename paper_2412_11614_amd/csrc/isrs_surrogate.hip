@@ -396,6 +396,7 @@ __global__ void __launch_bounds__(256, FB_MINB) mlp_fused_kernel(FusedArgs a)
 {
     __shared__ __attribute__((aligned(16))) __bf16 Hs[FB_M * LDH];
     __shared__ __attribute__((aligned(16))) __bf16 Xs[FB_M * LDX];
+    __shared__ float Os[4][FB_M];   // output-layer partial sums, one row per wave
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int64_t row0 = (int64_t)blockIdx.x * FB_M;
     for (int rr = tid; rr < FB_M; rr += 256) {
@@ -425,39 +426,64 @@ __global__ void __launch_bounds__(256, FB_MINB) mlp_fused_kernel(FusedArgs a)
             // register 4 g + e of tile (ft, rt) holds feature 64 w + 32 ft + 8 g + 4 (lane / 32) + e
             // of data row 32 rt + lane % 32: four consecutive features, one 8-byte write
             const float* bias = pm + B_OFF[l];
+            if (l < 3) {
+#pragma unroll
+                for (int ft = 0; ft < 2; ++ft)
+#pragma unroll
+                    for (int g = 0; g < 4; ++g) {
+                        const int f0 = 64 * w + 32 * ft + 8 * g + 4 * (lane >> 5);
+                        const float4 bq = *reinterpret_cast<const float4*>(bias + f0);
+                        const float bb[4] = {bq.x, bq.y, bq.z, bq.w};
+#pragma unroll
+                        for (int rt = 0; rt < FB_RT; ++rt) {
+                            bf4 hv;
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) {
+                                const float z = acc[ft][rt][4 * g + e] + bb[e];
+                                hv[e] = (__bf16)(z * sigm(z));
+                            }
+                            *reinterpret_cast<bf4*>(Hs + (32 * rt + lr) * LDH + f0) = hv;
+                        }
+                    }
+                __syncthreads();
+                continue;
+            }
+            // last hidden layer: the output layer o = H4 w5 + b5 straight from the
+            // accumulators, each activation rounded to BF16 as a stored H4 would be.
+            // A lane sums its 32 features of each row; the two half-waves hold the
+            // other 32 of the wave's 64, the four waves the rest.
+            const float* w5 = pm + OFF_W5;
+            float part[FB_RT];
+#pragma unroll
+            for (int rt = 0; rt < FB_RT; ++rt) part[rt] = 0.0f;
 #pragma unroll
             for (int ft = 0; ft < 2; ++ft)
 #pragma unroll
                 for (int g = 0; g < 4; ++g) {
                     const int f0 = 64 * w + 32 * ft + 8 * g + 4 * (lane >> 5);
                     const float4 bq = *reinterpret_cast<const float4*>(bias + f0);
-                    const float bb[4] = {bq.x, bq.y, bq.z, bq.w};
+                    const float4 wq = *reinterpret_cast<const float4*>(w5 + f0);
+                    const float bb[4] = {bq.x, bq.y, bq.z, bq.w}, ww[4] = {wq.x, wq.y, wq.z, wq.w};
 #pragma unroll
-                    for (int rt = 0; rt < FB_RT; ++rt) {
-                        bf4 hv;
+                    for (int rt = 0; rt < FB_RT; ++rt)
 #pragma unroll
                         for (int e = 0; e < 4; ++e) {
                             const float z = acc[ft][rt][4 * g + e] + bb[e];
-                            hv[e] = (__bf16)(z * sigm(z));
+                            part[rt] = fmaf((float)(__bf16)(z * sigm(z)), ww[e], part[rt]);
                         }
-                        *reinterpret_cast<bf4*>(Hs + (32 * rt + lr) * LDH + f0) = hv;
-                    }
                 }
+#pragma unroll
+            for (int rt = 0; rt < FB_RT; ++rt) part[rt] += __shfl_xor(part[rt], 32, 64);
+            if (lane < 32)
+#pragma unroll
+                for (int rt = 0; rt < FB_RT; ++rt) Os[w][32 * rt + lane] = part[rt];
             __syncthreads();
+            for (int rr = tid; rr < FB_M; rr += 256) {
+                const float o = ((Os[0][rr] + Os[1][rr]) + (Os[2][rr] + Os[3][rr])) + pm[OFF_B5];
+                if (row0 + rr < a.n) a.pred[(int64_t)m * a.n + row0 + rr] = a.shift + a.scale * o;
+            }
+            // the next writes to Os and Hs come after this member's last barrier
         }
-        // output layer: 256 / FB_M threads per row, split over the columns
-        {
-            constexpr int TPR = 256 / FB_M, CPT = NH / TPR;
-            const int rr = tid / TPR, part = tid % TPR;
-            const float* w5 = pm + OFF_W5 + CPT * part;
-            const __bf16* h = Hs + rr * LDH + CPT * part;
-            float s = 0.0f;
-#pragma unroll 8
-            for (int c = 0; c < CPT; ++c) s += (float)h[c] * w5[c];
-            if constexpr (TPR == 2) s += __shfl_xor(s, 1, 64);
-            if (part == 0 && row0 + rr < a.n) a.pred[(int64_t)m * a.n + row0 + rr] = a.shift + a.scale * (s + pm[OFF_B5]);
-        }
-        __syncthreads();  // the tile's activations are free for the next member
     }
 }
 
