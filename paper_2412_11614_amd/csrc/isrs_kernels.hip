@@ -19,8 +19,8 @@
 // s = exp(-2 alpha Delta) is a per-span constant.  g_k depends on the point
 // only through f1 + f2 (its anti-diagonal), so each thread owns PPT
 // consecutive points of one anti-diagonal and reads one staged LDS row for
-// all of them.  Phases are formed in FP64 in revolutions and reduced to
-// [-1/2, 1/2] before the sine / cosine.
+// all of them.  Phases are formed in FP64 in revolutions and reduced modulo
+// one revolution, in FP64, before the sine / cosine.
 #include "isrs_internal.h"
 
 #include <mutex>
